@@ -1,0 +1,166 @@
+"""Polynomial extrapolation weights and guesses (oracle; test infrastructure only).
+
+Follows §3 of the paper:
+
+* the guess is a fixed linear combination of the last M solutions, with the
+  first weight on the oldest stored solution (§3, eq. ExtrapExpn);
+* naive extrapolation through all M points has the binomial weights of the
+  theorem in §3.1 (eq. NaiveExtrapCoeffs);
+* stabilized extrapolation fits a degree-m polynomial in the least-squares
+  sense at the equispaced nodes t_i = -1 + (i-1) h, h = 2/(M-1), and evaluates
+  it at t = 1 + h, giving beta^T = v^T (V^T V)^{-1} V^T (§3.2, eq. LSQRCoeffs);
+* the Lebesgue constant of a scheme is the 1-norm of its weights (§6.5).
+
+Weights are computed in exact rational arithmetic (``fractions.Fraction``),
+with the monomial basis: the least-squares weights do not depend on the choice
+of polynomial basis, nor on an affine change of the time variable (§3.2).
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+from math import comb
+
+import numpy as np
+
+
+def time_nodes(M: int):
+    """Equispaced history nodes and the new node (§3.2).
+
+    For M = 1 the single history value sits at t = 0 and the new node at
+    t = 1; with one point only the constant fit exists, so any placement gives
+    the same weight (beta = [1], the previous-solution guess).
+    """
+    if M < 1:
+        raise ValueError("M must be >= 1")
+    if M == 1:
+        return [Fraction(0)], Fraction(1)
+    h = Fraction(2, M - 1)
+    t = [Fraction(-1) + (i - 1) * h for i in range(1, M + 1)]
+    return t, Fraction(1) + h
+
+
+def _solve_exact(G, rhs):
+    """Gauss-Jordan elimination on a small nonsingular rational system."""
+    n = len(G)
+    A = [list(G[r]) + [rhs[r]] for r in range(n)]
+    for col in range(n):
+        piv = next(r for r in range(col, n) if A[r][col] != 0)
+        A[col], A[piv] = A[piv], A[col]
+        p = A[col][col]
+        A[col] = [a / p for a in A[col]]
+        for r in range(n):
+            if r != col and A[r][col] != 0:
+                f = A[r][col]
+                A[r] = [a - f * b for a, b in zip(A[r], A[col])]
+    return [A[r][n] for r in range(n)]
+
+
+def vandermonde(M: int, m: int):
+    """V_ij = psi_j(t_i) with psi_j(t) = t^j, and v_j = psi_j(t_new) (§3.2)."""
+    t, tn = time_nodes(M)
+    V = [[ti ** j for j in range(m + 1)] for ti in t]
+    v = [tn ** j for j in range(m + 1)]
+    return V, v
+
+
+def beta_ls_exact(m: int, M: int):
+    """Least-squares extrapolation weights beta (length M) as Fractions.
+
+    beta = V (V^T V)^{-1} v, i.e. beta^T = v^T (V^T V)^{-1} V^T
+    (§3.2, eq. LSQRCoeffs).  Requires 0 <= m <= M - 1.
+    """
+    if not (0 <= m <= M - 1):
+        raise ValueError("need 0 <= m <= M-1")
+    V, v = vandermonde(M, m)
+    G = [[sum(V[i][a] * V[i][b] for i in range(M)) for b in range(m + 1)]
+         for a in range(m + 1)]
+    y = _solve_exact(G, v)
+    return [sum(V[i][j] * y[j] for j in range(m + 1)) for i in range(M)]
+
+
+def beta_naive_exact(M: int):
+    """Weights of Lagrange extrapolation through M equispaced points.
+
+    beta_i = (-1)^(M-i) C(M, i-1), i = 1..M (§3.1, theorem, eq.
+    NaiveExtrapCoeffs).
+    """
+    return [Fraction((-1) ** (M - i) * comb(M, i - 1)) for i in range(1, M + 1)]
+
+
+def lebesgue(beta) -> Fraction:
+    """Lebesgue constant Lambda = ||beta||_1 (§6.5)."""
+    return sum(abs(Fraction(b)) for b in beta)
+
+
+def to_f64(beta) -> np.ndarray:
+    """Round exact weights to FP64 once (correct rounding of each ratio)."""
+    return np.array([float(Fraction(b)) for b in beta], dtype=np.float64)
+
+
+def effective_params(m: int, M: int, k: int):
+    """Warm-up rule while the history holds only k < M solutions.
+
+    The paper does not treat the start of a sequence.  Reading used here:
+    with k stored solutions the guess is EXTRAP(min(m, k-1), k); k = 1 gives
+    the previous solution and k = 0 gives the zero guess.  Returns (m_eff, k)
+    or None for the zero guess.
+    """
+    k = min(k, M)
+    if k <= 0:
+        return None
+    return min(m, k - 1), k
+
+
+def form(history_oldest_first, beta) -> np.ndarray:
+    """x0 = sum_i beta_i x_{n-M+i}, summed oldest first (§3, eq. ExtrapExpn)."""
+    beta = np.asarray(beta, dtype=np.float64)
+    if len(history_oldest_first) != len(beta):
+        raise ValueError("history length and weight count differ")
+    acc = beta[0] * np.asarray(history_oldest_first[0], dtype=np.float64)
+    for b, x in zip(beta[1:], history_oldest_first[1:]):
+        acc = acc + b * np.asarray(x, dtype=np.float64)
+    return acc
+
+
+class ExtrapHistory:
+    """Last-M-solutions history with least-squares extrapolation (§3.2).
+
+    ``dtype`` selects the storage format of stored solutions (see
+    ``oracle.lowprec``); the guess itself is always evaluated in FP64 from the
+    stored (rounded) values, which is the exact value the GPU's FP32
+    accumulation approximates.
+    """
+
+    def __init__(self, M: int, m: int, dtype: str = "f64"):
+        if not (0 <= m <= M - 1):
+            raise ValueError("need 0 <= m <= M-1")
+        self.M, self.m, self.dtype = M, m, dtype
+        self.hist = []          # oldest first, stored values as float64 arrays
+        self._cache = {}
+
+    def weights(self, k: int):
+        p = effective_params(self.m, self.M, k)
+        if p is None:
+            return None
+        if p not in self._cache:
+            self._cache[p] = to_f64(beta_ls_exact(*p))
+        return self._cache[p]
+
+    def form(self, b=None, N=None) -> np.ndarray:
+        k = len(self.hist)
+        if k == 0:
+            n = N if N is not None else (len(b) if b is not None else None)
+            if n is None:
+                raise ValueError("need N for an empty history")
+            return np.zeros(n, dtype=np.float64)
+        return form(self.hist, self.weights(k))
+
+    def update(self, x) -> None:
+        from .lowprec import round_store
+
+        self.hist.append(round_store(np.asarray(x, dtype=np.float64), self.dtype))
+        if len(self.hist) > self.M:
+            self.hist.pop(0)
+
+    def reset(self) -> None:
+        self.hist = []
