@@ -1,0 +1,262 @@
+#!/usr/bin/env python3
+"""Benchmark of the initial-guess hot path on one MI355X.
+
+Workload (defaults): 7-point Helmholtz (-Laplacian_h + 10 I) on a 256^3 grid
+of the unit cube (16,777,216 unknowns), right-hand sides b_n = sum of 16
+seeded plane-wave modes with amplitudes sin(w_k t_n + phi_k), dt = 0.005.
+One step = one time step of the whole hot path for every method:
+  b_n (device RHS kernel) -> guess_form -> Jacobi-PCG to ||r|| <= 1e-8 ||b||
+  -> guess_update,
+for least-squares extrapolation EXTRAP(2, 8) and A-orthonormal projection
+PROJ(8), both with FP64 history.  W warm-up steps fill the histories first.
+
+value = guess form+update HBM throughput in GB/s: algorithmic bytes of every
+guess kernel in the timed steps divided by their device time (HIP events on
+the library's stream).  PCG iterations and ms per step are reported per
+method.  The JSON line also carries the roofline of the dominant guess kernel
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# kernels launched per call, in order (see include/libguess.h, guess_kernel_times)
+KERNELS = {
+    ("extrap", "form"): ["extrap_form"],
+    ("extrap", "update"): ["ring_store"],
+    ("last", "form"): ["extrap_form"],
+    ("last", "update"): ["ring_store"],
+    ("proj", "form"): ["proj_dots", "proj_combine"],
+    ("proj", "update"): ["proj_apply", "proj_reorth", "proj_gs_write"],
+}
+
+
+def kernel_bytes(method, call, N, s, k_or_d, M, restart):
+    """Algorithmic HBM bytes of each kernel of one call (list, launch order)."""
+    if method in ("extrap", "last"):
+        if call == "form":
+            return [N * (k_or_d * s + 8)] if k_or_d > 0 else []
+        return [N * (8 + s)]
+    d = k_or_d
+    if call == "form":
+        return [N * (d * s + 8) if d > 0 else 0, N * (d * s + 8)]
+    if restart:
+        return [N * (8 + 2 * s), 0, 0]
+    return [N * (16 + d * s), N * (2 * d * s + 8), N * (2 * d * s + 16 + 2 * s)]
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=10)
+    p.add_argument("--n", type=int, default=256)
+    p.add_argument("--M", type=int, default=8)
+    p.add_argument("--degree", type=int, default=2)
+    p.add_argument("--modes", type=int, default=16)
+    p.add_argument("--dt", type=float, default=0.005)
+    p.add_argument("--seed", type=int, default=0)
+    p.add_argument("--rtol", type=float, default=1e-8)
+    p.add_argument("--dtype", default="f64", choices=["f64", "f32", "f16", "bf16"])
+    p.add_argument("--methods", default="extrap,proj")
+    p.add_argument("--maxit", type=int, default=5000)
+    p.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
+    p.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
+    p.add_argument("--cpu-steps", type=int, default=2)
+    return p.parse_args()
+
+
+def cpu_baseline(args, s_bytes):
+    """The oracle (NumPy FP64) timed on the host: guess form+update on a bounded sample.
+
+    Sample: `cpu_steps` steady-state steps of EXTRAP(m, M) and PROJ(M) at the
+    benchmark grid, full histories of random vectors; the oracle's own
+    operator is applied once per projection update.  Reported in the same
+    algorithmic GB/s as the GPU value.
+    """
+    import numpy as np
+
+    from oracle import operator as oop
+    from oracle.extrap import ExtrapHistory
+    from oracle.projection import AOrthoProjection
+
+    n, M, m = args.n, args.M, args.degree
+    N = n ** 3
+    rng = np.random.default_rng(1)
+    Aop = oop.Operator(n)
+    e = ExtrapHistory(M, m)
+    for _ in range(M):
+        e.update(rng.standard_normal(N))
+    P = AOrthoProjection(M, Aop, 1e-6)
+    for _ in range(M - 2):
+        P.update(rng.standard_normal(N))
+    b = rng.standard_normal(N)
+    nbytes, secs = 0.0, 0.0
+    for _ in range(args.cpu_steps):
+        x = rng.standard_normal(N)
+        t0 = time.perf_counter()
+        e.form(b)
+        e.update(x)
+        secs += time.perf_counter() - t0
+        nbytes += N * (M * 8 + 8) + N * 16
+        d = P.d
+        t0 = time.perf_counter()
+        P.form(b)
+        P.update(x)
+        secs += time.perf_counter() - t0
+        restart = d == 0 or d >= M
+        nbytes += 2 * N * (d * 8 + 8) + (N * (8 + 16) if restart else N * (5 * d * 8 + 16 + 40))
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    return {
+        "value": nbytes / secs / 1e9,
+        "unit": "GB/s",
+        "cores": 1,
+        "cores_available": cores,
+        "kind": "oracle",
+        "sample": f"{args.cpu_steps} steady-state steps of EXTRAP({m},{M}) + PROJ({M}) form+update "
+                  f"at {n}^3, FP64 NumPy (elementwise streaming is single-threaded), {secs:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout "
+              "is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2009_10863_amd import libguess as L
+    from paper_2009_10863_amd.sequence import Operator, PlaneWaveRHS
+
+    torch.cuda.set_device(0)
+    n, N, M = args.n, args.n ** 3, args.M
+    s = L.ELEM_BYTES[L.DTYPES[args.dtype]]
+    methods = [m.strip() for m in args.methods.split(",") if m.strip()]
+    op = Operator(n, 10.0)
+    params = synth.plane_wave_params(args.seed, args.modes)
+    rhs = PlaneWaveRHS(params, n)
+    b = torch.empty(N, dtype=torch.float64, device="cuda")
+    ctx, xs = {}, {}
+    for m in methods:
+        ctx[m] = L.guess_create_ex(N, 1 if m == "last" else M, L.METHODS[m], args.degree if m == "extrap" else 0,
+                                   L.DTYPES[args.dtype], 1e-6, op.handle, L.stream_handle())
+        L.guess_profile(ctx[m], True)
+        xs[m] = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    stats = {m: {"iters": [], "guess_ms": 0.0, "guess_bytes": 0.0, "solve_ms": 0.0, "relres": []} for m in methods}
+    kstat = {}    # kernel -> [launches, ms, bytes]
+
+    def one_step(step, timed):
+        t = step * args.dt
+        rhs(t, b)
+        for m in methods:
+            g, x = ctx[m], xs[m]
+            inf0 = L.guess_get_info(g)
+            kd = inf0["count"]
+            kd_form = min(kd, M) if m != "proj" else kd
+            L.guess_form(g, b, x)
+            tf = L.guess_kernel_times(g)
+            ev[0].record()
+            st, it, rr = op.solve(b, x, args.rtol, args.maxit)
+            ev[1].record()
+            inf1 = L.guess_get_info(g)
+            L.guess_update(g, x)
+            tu = L.guess_kernel_times(g)
+            if not timed:
+                continue
+            torch.cuda.synchronize()
+            S = stats[m]
+            S["iters"].append(it)
+            S["relres"].append(rr)
+            S["solve_ms"] += ev[0].elapsed_time(ev[1])
+            restart = m == "proj" and (inf1["count"] == 0 or inf1["count"] >= M)
+            for call, times, kdd in (("form", tf, kd_form), ("update", tu, inf1["count"])):
+                names = KERNELS[(m, call)]
+                byts = kernel_bytes(m, call, N, s, kdd, M, restart)
+                for name, ms, by in zip(names, times, byts):
+                    if by == 0:
+                        continue
+                    ks = kstat.setdefault(name, [0, 0.0, 0.0])
+                    ks[0] += 1
+                    ks[1] += ms
+                    ks[2] += by
+                    S["guess_ms"] += ms
+                    S["guess_bytes"] += by
+            if st != L.OK:
+                raise RuntimeError(f"PCG failed for {m} at step {step}: status {st}")
+
+    for step in range(1, args.warmup + 1):
+        one_step(step, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for step in range(args.warmup + 1, args.warmup + args.steps + 1):
+        one_step(step, True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    tot_bytes = sum(S["guess_bytes"] for S in stats.values())
+    tot_ms = sum(S["guess_ms"] for S in stats.values())
+    value = tot_bytes / (tot_ms * 1e-3) / 1e9
+    dom = max(kstat.items(), key=lambda kv: kv[1][1])
+    dname, (dl, dms, dby) = dom
+    achieved = (dby / dl) / (dms / dl * 1e-3) / 1e9
+    per_method = {}
+    for m, S in stats.items():
+        per_method[m] = {
+            "guess_GBps": S["guess_bytes"] / (S["guess_ms"] * 1e-3) / 1e9 if S["guess_ms"] else None,
+            "guess_ms_per_step": S["guess_ms"] / args.steps,
+            "pcg_iters_per_step": float(np.mean(S["iters"])),
+            "pcg_ms_per_step": S["solve_ms"] / args.steps,
+            "max_relres": float(np.max(S["relres"])),
+        }
+    kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / v[0], "GBps": v[2] / (v[1] * 1e-3) / 1e9,
+                   "bytes_per_launch": v[2] / v[0]} for k, v in sorted(kstat.items())}
+    out = {
+        "metric": "guess form+update HBM GB/s (256^3, M=8); PCG iters & ms/step vs FP64 plain",
+        "value": value,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"helmholtz7 {n}^3 ({N} unknowns), {args.modes} plane-wave modes, dt={args.dt}, "
+                               f"M={M}, EXTRAP({args.degree},{M}) + PROJ({M}), {args.dtype} history, PCG rtol {args.rtol}",
+                   "n": n, "N": N, "M": M, "degree": args.degree, "methods": methods,
+                   "history_dtype": args.dtype, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": dby / dl, "avg_us": 1e3 * dms / dl},
+        "methods": per_method,
+        "kernels": kernels,
+    }
+    if args.cpu:
+        out["cpu_baseline"] = cpu_baseline(args, s)
+    for g in ctx.values():
+        L.guess_destroy(g)
+    op.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,251 @@
+/*
+ * libguess -- initial guesses for sequences of SPD linear solves, MI355X (gfx950).
+ *
+ * Method: A. P. Austin, N. Chalmers, T. Warburton, "Initial Guesses for
+ * Sequences of Linear Systems in a GPU-Accelerated Incompressible Flow
+ * Solver" (2020).  Two guess methods are provided:
+ *
+ *   - stabilized least-squares polynomial extrapolation (§3.2, eq.
+ *     LSQRCoeffs; the guess is the fixed combination of eq. ExtrapExpn),
+ *     with the previous-solution guess as its M = 1 case (§3.1);
+ *   - Fischer's projection, classic restart variant (§2, Algorithm 1), in
+ *     A-orthonormal form: the history keeps X with X^T A X = I and B = A X,
+ *     the guess is X (X^T b), and each update applies A once and runs
+ *     twice-iterated classical Gram-Schmidt in the A inner product.
+ *
+ * around a matrix-free 7-point Helmholtz / variable-coefficient operator
+ * and a Jacobi-preconditioned CG (§5.3) that judges the guesses.
+ *
+ * Conventions (every entry point):
+ *   - Vectors are FP64, length N, on the device of the calling thread's
+ *     current HIP device, owned by the caller.  The library never frees or
+ *     retains caller memory beyond the call.
+ *   - Grids are n_x x n_y x n_z interior nodes, flattened with x fastest;
+ *     boundary values are the Dirichlet value 0 and are not stored.
+ *   - Work is enqueued on the stream bound to the context or operator
+ *     (NULL = the null stream).  guess_form, guess_update and op_apply return
+ *     without a host synchronisation; pcg_solve and guess_get_info
+ *     synchronise that stream.
+ *   - Every function returns a status code (GUESS_OK = 0 or a negative
+ *     error); no C++ exception crosses the boundary.  guess_last_error()
+ *     gives a message for the calling thread's last failure.
+ *   - A context or operator must not be used from two threads at once;
+ *     distinct contexts are independent.
+ */
+#ifndef LIBGUESS_H
+#define LIBGUESS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct guess_ctx *guess_t;
+typedef struct guess_op *guess_op_t;
+
+/* guess methods */
+enum {
+    GUESS_ZERO = 0,   /* x0 = 0                                                    */
+    GUESS_LAST = 1,   /* x0 = previous solution (extrapolation with M = 1, §3.1)    */
+    GUESS_EXTRAP = 2, /* least-squares extrapolation of degree m over M solutions  */
+    GUESS_PROJ = 3    /* A-orthonormal projection, classic restart (§2, Alg. 1)     */
+};
+
+/* storage format of the history vectors */
+enum { GUESS_F64 = 0, GUESS_F32 = 1, GUESS_F16 = 2, GUESS_BF16 = 3 };
+
+/* status codes */
+enum {
+    GUESS_OK = 0,
+    GUESS_EINVAL = -1,      /* invalid argument                        */
+    GUESS_ENOMEM = -2,      /* device allocation failed                */
+    GUESS_EHIP = -3,        /* HIP runtime error                       */
+    GUESS_ENOTCONV = -4,    /* pcg_solve: maxit reached                */
+    GUESS_EBREAKDOWN = -5,  /* pcg_solve: p^T A p <= 0 or not finite  */
+    GUESS_ENONFINITE = -6   /* non-finite value where one is required  */
+};
+
+/* PCG stopping rules (§6.4) */
+enum {
+    GUESS_STOP_RHS = 0,       /* ||r|| <= rtol ||b||                                   */
+    GUESS_STOP_INITRESID = 1  /* ||r|| <  rtol max(||r0||, 1): the paper's default rule */
+};
+
+/* ------------------------------------------------------------------ operator */
+
+/*
+ * Create the operator A on an nx x ny x nz grid of interior nodes:
+ *   kappa == NULL:  (Au)_i = inv_h2 (6 u_i - sum_nb u_nb) + shift u_i
+ *   kappa != NULL:  (Au)_i = inv_h2 sum_faces k_f (u_i - u_nb) + shift u_i,
+ *                   k_f = 2 k_i k_nb / (k_i + k_nb),
+ * with kappa a device array of nodal values on all (nx+2)(ny+2)(nz+2) nodes
+ * (boundary included, x fastest), read once here and not retained.  For the
+ * unit cube with n^3 interior nodes inv_h2 = (n+1)^2.  Neighbour order and
+ * rounding are fixed: west, east, south, north, bottom, top, summed left to
+ * right without fused multiply-add, then inv_h2 * s + shift * u.
+ * Requires nx, ny, nz >= 1, inv_h2 > 0, shift >= 0; EINVAL otherwise.
+ */
+int guess_op_create(int nx, int ny, int nz, double inv_h2, double shift,
+                    const double *kappa, guess_op_t *out);
+void guess_op_destroy(guess_op_t A);
+/* Bind a hipStream_t (passed as void*) to the operator and its PCG. */
+int guess_op_set_stream(guess_op_t A, void *stream);
+/* Number of unknowns nx*ny*nz. */
+int64_t guess_op_size(guess_op_t A);
+
+/* y = A x.  x and y must not alias. */
+int op_apply(guess_op_t A, const double *x, double *y);
+
+/*
+ * Jacobi-preconditioned CG (§5.3) for A x = b.  x holds the initial guess on
+ * entry and the solution on exit.  Stops when the recurrence residual meets
+ * the rule (GUESS_STOP_RHS or GUESS_STOP_INITRESID) with tolerance rtol, the
+ * test also applied before the first iteration (a guess that already meets
+ * it costs 0 iterations).  On return *iters = number of operator
+ * applications in the loop, *relres = ||r|| / ||b|| (||r|| when b = 0).
+ * Returns GUESS_OK, GUESS_ENOTCONV (maxit reached; x holds the last iterate)
+ * or GUESS_EBREAKDOWN.  iters / relres may be NULL.  Synchronises the stream.
+ */
+int pcg_solve(guess_op_t A, const double *b, double *x, double rtol, int maxit,
+              int *iters, double *relres);
+int pcg_solve_ex(guess_op_t A, const double *b, double *x, double rtol, int maxit,
+                 int stop_rule, int *iters, double *relres);
+
+/* ------------------------------------------------------------------ guesses */
+
+typedef struct guess_opts {
+    int64_t N;          /* vector length, >= 1                                      */
+    int M;              /* history size, 1 <= M <= GUESS_MAX_M                      */
+    int method;         /* GUESS_ZERO / LAST / EXTRAP / PROJ                         */
+    int degree;         /* EXTRAP: polynomial degree m, 0 <= m <= M - 1              */
+    int dtype;          /* storage format of the history (GUESS_F64 ...)             */
+    double eps_rel;     /* PROJ: reject if nu <= eps_rel * nu0; <= 0 selects 1e-6    */
+    guess_op_t op;      /* PROJ: operator applied in guess_update when Ax == NULL    */
+    void *stream;       /* hipStream_t; NULL = null stream                           */
+} guess_opts;
+
+#define GUESS_MAX_M 16
+
+/*
+ * Create a context with FP64 history, eps_rel = 1e-6, no operator, the null
+ * stream.  LAST forces M = 1.  Returns NULL on failure (see guess_last_error).
+ */
+guess_t guess_create(int64_t N, int M, int method, int degree);
+int guess_create_ex(const guess_opts *o, guess_t *out);
+void guess_destroy(guess_t g);
+int guess_set_stream(guess_t g, void *stream);
+int guess_set_op(guess_t g, guess_op_t A);
+/* Device bytes the history and scratch of such a context occupy. */
+size_t guess_workspace_bytes(int64_t N, int M, int method, int dtype);
+
+/*
+ * Form the initial guess x0 for right-hand side b.
+ *   EXTRAP / LAST: x0 = sum_j beta_j h_j over the k stored solutions, oldest
+ *     first (eq. ExtrapExpn), with beta the least-squares weights of degree
+ *     min(m, k-1) over k nodes (warm-up while k < M); x0 = 0 when k = 0.
+ *     b is not read and may be NULL.  x0 may alias the caller's solve buffer.
+ *   PROJ: x0 = X (X^T b), x0 = 0 when the history is empty.  b is required
+ *     and must not alias x0.
+ *   ZERO: x0 = 0.
+ * FP64 history accumulates in FP64; reduced-precision history is read,
+ * widened and accumulated in FP32 (extrapolation) or FP64 (projection).
+ */
+int guess_form(guess_t g, const double *b, double *x0);
+
+/*
+ * Add the solution x of the latest solve to the history.
+ *   EXTRAP / LAST: x is rounded to the storage format into the next ring slot.
+ *   PROJ: Ax = A x if the caller has it (Ax = b is allowed, then
+ *     X^T A X = I holds only to the solve tolerance); Ax == NULL makes the
+ *     library apply the bound operator once (EINVAL if none is bound).
+ *     Restart when the history is empty or full (slot 1 <- x / ||x||_A);
+ *     otherwise two classical Gram-Schmidt passes in the A inner product,
+ *     then the new pair is kept iff nu > eps_rel * nu0 (nu, nu0 the A-norms
+ *     after / before orthogonalisation).  The decision is taken on the
+ *     device; a non-finite nu rejects the vector and sets a sticky flag.
+ *   ZERO: nothing.
+ */
+int guess_update(guess_t g, const double *x, const double *Ax);
+
+typedef struct guess_info {
+    int64_t N;
+    int method, dtype, M, degree;
+    int count;          /* EXTRAP/LAST: stored solutions (<= M); PROJ: columns d      */
+    int head;           /* EXTRAP/LAST: ring slot the next update writes              */
+    int last_accepted;  /* PROJ: 1 if the last update stored its vector                */
+    int restarts;       /* PROJ: restarts so far                                       */
+    int rejects;        /* PROJ: rejected vectors so far                               */
+    int nonfinite;      /* sticky: a non-finite norm or value was met                  */
+    double nu, nu0;     /* PROJ: last A-norms after / before Gram-Schmidt             */
+    double form_bytes;  /* algorithmic HBM bytes of the last guess_form                */
+    double update_bytes;/* algorithmic HBM bytes of the last guess_update              */
+} guess_info;
+
+/* Snapshot of the context state.  Synchronises the context's stream. */
+int guess_get_info(guess_t g, guess_info *info);
+/* Empty the history (EXTRAP: count = 0; PROJ: d = 0). */
+int guess_reset(guess_t g);
+
+/*
+ * Least-squares extrapolation weights of degree m over k equispaced
+ * solutions (§3.2, eq. LSQRCoeffs), computed on the host in FP64 with a
+ * Legendre basis and Householder QR.  beta[0] multiplies the oldest
+ * solution.  Requires 1 <= k <= GUESS_MAX_M, 0 <= m <= k - 1.
+ */
+int guess_extrap_weights(int m, int k, double *beta);
+
+/* Copy stored history vector j (PROJ: column j of X (which = 0) or B
+ * (which = 1), scale applied; EXTRAP: j-th oldest stored solution) into
+ * the FP64 device vector out.  For tests and checkpoints; synchronises. */
+int guess_history_get(guess_t g, int which, int j, double *out);
+
+/*
+ * Per-kernel timing (tracing aid).  With profiling enabled the library
+ * records a HIP event on the context's stream before and after every kernel
+ * that guess_form / guess_update launch for this context.
+ * guess_kernel_times waits for the most recent such call and returns the
+ * device time of each of its kernels in launch order (ms[0..*n-1]):
+ *   EXTRAP/LAST form: extrap_form;  update: ring_store
+ *   PROJ form: proj_dots, proj_combine;  update: proj_apply, proj_reorth,
+ *   proj_gs_write (the last two return at once after a restart)
+ * *n = 0 when profiling is off or the last call launched no kernel.
+ */
+int guess_profile(guess_t g, int enable);
+int guess_kernel_times(guess_t g, double *ms, int max, int *n);
+
+/* ------------------------------------------------------------------ workload */
+
+/*
+ * Right-hand side of a plane-wave workload on an n^3 unit-cube grid:
+ *   b_i = sum_k a_k cos(2 pi (kx_k x + ky_k y + kz_k z) + theta_k)
+ * at interior node (x, y, z) = (i, j, l) / (n + 1).  kvec: host int array
+ * 3K (kx, ky, kz per mode); theta, amp: host arrays of K doubles.  b is a
+ * device vector of n^3 doubles.  K <= 64.  Enqueued on `stream`.
+ */
+int workload_plane_wave_rhs(int n, int K, const int *kvec, const double *theta,
+                            const double *amp, double *b, void *stream);
+
+/* ------------------------------------------------------------------ vectors */
+
+/* out[k] = <v_k, y> for K device vectors v_k = V + k * N (K <= 64), FP64;
+ * deterministic two-stage reduction; out is a host array.  Synchronises. */
+int vec_multidot(int64_t N, int K, const double *V, const double *y, double *out,
+                 void *stream);
+/* y = sum_k c_k v_k (c host array of K doubles, V as above). */
+int vec_combine(int64_t N, int K, const double *V, const double *c, double *y,
+                void *stream);
+
+/* ------------------------------------------------------------------ misc */
+
+const char *guess_strerror(int code);
+const char *guess_last_error(void);
+/* Plain device copy dst <- src of `bytes` bytes with a hand-written kernel
+ * (bandwidth reference for the roofline). */
+int guess_copy_kernel(void *dst, const void *src, size_t bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBGUESS_H */

@@ -29,6 +29,7 @@ class AOrthoProjection:
         self.X = []          # A-orthonormal solution history
         self.B = []          # B = A X
         self.raw = []        # raw solutions accepted since the last restart
+        self.ratios = []     # nu / nu0 of each stored column when it was accepted
         self.last_accepted = None
         self.last_nu = None
         self.last_nu0 = None
@@ -36,6 +37,17 @@ class AOrthoProjection:
     @property
     def d(self) -> int:
         return len(self.X)
+
+    @property
+    def amplification(self) -> float:
+        """max nu0 / nu over the stored columns (1 for an empty history).
+
+        Rounding errors of size u in a column accepted with ratio nu/nu0 are
+        amplified by nu0/nu in the normalised column, so two correct FP64
+        implementations of this algorithm agree on the guess only to about
+        u times this factor.
+        """
+        return max([1.0] + [1.0 / r for r in self.ratios])
 
     def form(self, b) -> np.ndarray:
         """x0 = X (X^T b), or 0 when the history is empty (Algorithm 1, first step)."""
@@ -65,12 +77,13 @@ class AOrthoProjection:
         nu0 = float(np.sqrt(xt @ bt)) if (xt @ bt) >= 0 else float("nan")
         self.last_nu0 = nu0
         if self.d == 0 or self.d >= self.M:
-            self.X, self.B, self.raw = [], [], []
+            self.X, self.B, self.raw, self.ratios = [], [], [], []
             ok = np.isfinite(nu0) and nu0 > 0.0
             if ok:
                 self.X.append(self._store(xt / nu0))
                 self.B.append(self._store(bt / nu0))
                 self.raw.append(np.array(x, dtype=np.float64, copy=True))
+                self.ratios.append(1.0)
             self.last_nu = nu0
             self.last_accepted = bool(ok)
             return bool(ok)
@@ -87,11 +100,12 @@ class AOrthoProjection:
             self.X.append(self._store(xt / nu))
             self.B.append(self._store(bt / nu))
             self.raw.append(np.array(x, dtype=np.float64, copy=True))
+            self.ratios.append(nu / nu0)
         self.last_accepted = ok
         return ok
 
     def reset(self) -> None:
-        self.X, self.B, self.raw = [], [], []
+        self.X, self.B, self.raw, self.ratios = [], [], [], []
 
 
 def brute_force_guess(S, apply_A, b) -> np.ndarray:

@@ -1,0 +1,176 @@
+// Polynomial-extrapolation guess kernels (§3, eq. ExtrapExpn).
+//
+// extrap_form:  x0 = sum_{j<k} beta_j h_j, h_0 the oldest stored solution.
+//   One pass over the k ring slots and one FP64 store: (k s + 8) bytes per
+//   unknown, s the stored element size.  Each thread streams 4 consecutive
+//   unknowns of every slot (all k loads issued before the FMA chain), with
+//   non-temporal hints since nothing is reused.  FP64 history accumulates in
+//   FP64; FP32/FP16/BF16 history is widened and accumulated in FP32.
+// ring_store:   slot <- round(x): 8 + s bytes per unknown.
+#include "common.h"
+#include "launch.h"
+
+namespace lg {
+
+struct ExtrapArgs {
+    const void *slot[GUESS_MAX_M];
+    double beta[GUESS_MAX_M];
+};
+
+template <int DT, int K>
+__global__ __launch_bounds__(kBlock) void extrap_form_kernel(ExtrapArgs a, double *__restrict__ x0,
+                                                             int64_t N) {
+    const int64_t nc = N >> 2;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
+        if constexpr (DT == GUESS_F64) {
+            V4 h[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) h[j] = load4<DT>(a.slot[j], c);
+            V4 acc;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc.v[e] = a.beta[0] * h[0].v[e];
+#pragma unroll
+            for (int j = 1; j < K; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc.v[e] = __builtin_fma(a.beta[j], h[j].v[e], acc.v[e]);
+            store4<GUESS_F64>(x0, c, acc);
+        } else {
+            F4 h[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) h[j] = load4f<DT>(a.slot[j], c);
+            float acc[4];
+            const float b0 = (float)a.beta[0];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = b0 * h[0].v[e];
+#pragma unroll
+            for (int j = 1; j < K; ++j) {
+                const float bj = (float)a.beta[j];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[e] = __builtin_fmaf(bj, h[j].v[e], acc[e]);
+            }
+            V4 out{{(double)acc[0], (double)acc[1], (double)acc[2], (double)acc[3]}};
+            store4<GUESS_F64>(x0, c, out);
+        }
+    }
+    // ragged tail (N mod 4 unknowns), same arithmetic
+    const int rem = (int)(N & 3);
+    if (blockIdx.x == 0 && threadIdx.x < rem) {
+        const int64_t i = (nc << 2) + threadIdx.x;
+        if constexpr (DT == GUESS_F64) {
+            double acc = a.beta[0] * load1<DT>(a.slot[0], i);
+            for (int j = 1; j < K; ++j) acc = __builtin_fma(a.beta[j], load1<DT>(a.slot[j], i), acc);
+            x0[i] = acc;
+        } else {
+            float acc = (float)a.beta[0] * (float)load1<DT>(a.slot[0], i);
+            for (int j = 1; j < K; ++j)
+                acc = __builtin_fmaf((float)a.beta[j], (float)load1<DT>(a.slot[j], i), acc);
+            x0[i] = (double)acc;
+        }
+    }
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void ring_store_kernel(const double *__restrict__ x,
+                                                            void *__restrict__ slot, int64_t N) {
+    const int64_t nc = N >> 2;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride)
+        store4<DT>(slot, c, load4<GUESS_F64>(x, c));
+    const int rem = (int)(N & 3);
+    if (blockIdx.x == 0 && threadIdx.x < rem) {
+        const int64_t i = (nc << 2) + threadIdx.x;
+        store1<DT>(slot, i, x[i]);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void fill_zero_kernel(double *__restrict__ x, int64_t N) {
+    const int64_t nc = N >> 2;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const V4 z{{0.0, 0.0, 0.0, 0.0}};
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride)
+        store4<GUESS_F64>(x, c, z);
+    const int rem = (int)(N & 3);
+    if (blockIdx.x == 0 && threadIdx.x < rem) x[(nc << 2) + threadIdx.x] = 0.0;
+}
+
+template <int DT>
+__global__ __launch_bounds__(kBlock) void widen_kernel(const void *__restrict__ src, double scale,
+                                                       double *__restrict__ out, int64_t N) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N; i += stride)
+        out[i] = scale * load1<DT>(src, i);
+}
+
+int launch_widen(int dtype, const void *src, double scale, double *out, int64_t N, hipStream_t s) {
+    const int grid = stream_grid(N, grid_cap());
+    switch (dtype) {
+        case GUESS_F64: widen_kernel<GUESS_F64><<<grid, kBlock, 0, s>>>(src, scale, out, N); break;
+        case GUESS_F32: widen_kernel<GUESS_F32><<<grid, kBlock, 0, s>>>(src, scale, out, N); break;
+        case GUESS_F16: widen_kernel<GUESS_F16><<<grid, kBlock, 0, s>>>(src, scale, out, N); break;
+        case GUESS_BF16: widen_kernel<GUESS_BF16><<<grid, kBlock, 0, s>>>(src, scale, out, N); break;
+        default: return GUESS_EINVAL;
+    }
+    return GUESS_OK;
+}
+
+template <int DT, int K>
+static void run_form(const ExtrapArgs &a, double *x0, int64_t N, int grid, hipStream_t s) {
+    extrap_form_kernel<DT, K><<<grid, kBlock, 0, s>>>(a, x0, N);
+}
+
+template <int DT>
+static int form_dt(int k, const ExtrapArgs &a, double *x0, int64_t N, int grid, hipStream_t s) {
+    switch (k) {
+#define LG_K(KK) case KK: run_form<DT, KK>(a, x0, N, grid, s); break;
+        LG_K(1) LG_K(2) LG_K(3) LG_K(4) LG_K(5) LG_K(6) LG_K(7) LG_K(8)
+        LG_K(9) LG_K(10) LG_K(11) LG_K(12) LG_K(13) LG_K(14) LG_K(15) LG_K(16)
+#undef LG_K
+        default: return GUESS_EINVAL;
+    }
+    return GUESS_OK;
+}
+
+int launch_extrap_form(int dtype, int k, const void *const *slots, const double *beta, double *x0,
+                       int64_t N, hipStream_t s, KEvents *ev) {
+    if (k < 1 || k > GUESS_MAX_M) return GUESS_EINVAL;
+    ExtrapArgs a{};
+    for (int j = 0; j < k; ++j) {
+        a.slot[j] = slots[j];
+        a.beta[j] = beta[j];
+    }
+    const int grid = stream_grid(N >> 2, grid_cap());
+    int rc = GUESS_EINVAL;
+    kev(ev, 0, s);
+    switch (dtype) {
+        case GUESS_F64: rc = form_dt<GUESS_F64>(k, a, x0, N, grid, s); break;
+        case GUESS_F32: rc = form_dt<GUESS_F32>(k, a, x0, N, grid, s); break;
+        case GUESS_F16: rc = form_dt<GUESS_F16>(k, a, x0, N, grid, s); break;
+        case GUESS_BF16: rc = form_dt<GUESS_BF16>(k, a, x0, N, grid, s); break;
+    }
+    kev(ev, 1, s);
+    if (ev) ev->count = 1;
+    return rc;
+}
+
+int launch_ring_store(int dtype, const double *x, void *slot, int64_t N, hipStream_t s, KEvents *ev) {
+    const int grid = stream_grid(N >> 2, grid_cap());
+    kev(ev, 0, s);
+    if (ev) ev->count = 1;
+    switch (dtype) {
+        case GUESS_F64: ring_store_kernel<GUESS_F64><<<grid, kBlock, 0, s>>>(x, slot, N); break;
+        case GUESS_F32: ring_store_kernel<GUESS_F32><<<grid, kBlock, 0, s>>>(x, slot, N); break;
+        case GUESS_F16: ring_store_kernel<GUESS_F16><<<grid, kBlock, 0, s>>>(x, slot, N); break;
+        case GUESS_BF16: ring_store_kernel<GUESS_BF16><<<grid, kBlock, 0, s>>>(x, slot, N); break;
+        default: return GUESS_EINVAL;
+    }
+    kev(ev, 1, s);
+    return GUESS_OK;
+}
+
+int launch_fill_zero(double *x, int64_t N, hipStream_t s) {
+    fill_zero_kernel<<<stream_grid(N >> 2, grid_cap()), kBlock, 0, s>>>(x, N);
+    return GUESS_OK;
+}
+
+}  // namespace lg

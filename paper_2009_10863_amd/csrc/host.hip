@@ -1,0 +1,753 @@
+// libguess C ABI: contexts, operators, PCG driver and the host-side
+// least-squares weight solver.  Every device step runs in the kernels of
+// extrap.hip, proj.hip, op.hip and vec.hip; this file only allocates,
+// validates arguments, keeps host-side bookkeeping and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "launch.h"
+#include "libguess.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(GUESS_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define LG_HIP(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+#define LG_TRY(expr)                \
+    do {                            \
+        int r_ = (expr);            \
+        if (r_ != GUESS_OK) return r_; \
+    } while (0)
+
+int check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return GUESS_OK;
+}
+
+int esize(int dtype) {
+    switch (dtype) {
+        case GUESS_F64: return 8;
+        case GUESS_F32: return 4;
+        case GUESS_F16: return 2;
+        case GUESS_BF16: return 2;
+    }
+    return 0;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Stride between stored columns / ring slots: a multiple of 128 elements, so
+// every column starts 256-byte aligned for every storage format.
+int64_t col_stride(int64_t N) { return (N + 127) / 128 * 128; }
+
+int env_int(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    return std::atoi(v);
+}
+
+}  // namespace
+
+namespace lg {
+
+int grid_cap() {
+    static const int v = [] {
+        int x = env_int("LIBGUESS_GRID_CAP", 1 << 20);
+        return x < 1 ? 1 : x;
+    }();
+    return v;
+}
+
+int reduce_blocks() {
+    static const int v = [] {
+        int x = env_int("LIBGUESS_REDUCE_BLOCKS", 1024);
+        if (x < 1) x = 1;
+        if (x > kMaxPartialBlocks) x = kMaxPartialBlocks;
+        return x;
+    }();
+    return v;
+}
+
+}  // namespace lg
+
+// ====================================================================== operator
+struct guess_op {
+    lg::Grid g{};
+    hipStream_t stream = nullptr;
+    double *kx = nullptr, *ky = nullptr, *kz = nullptr, *dinv = nullptr;
+    double *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;
+    lg::PcgState *st = nullptr;
+    lg::PcgState *host_st = nullptr;  // pinned
+};
+
+static void op_free(guess_op *A) {
+    if (!A) return;
+    for (void *ptr : {(void *)A->kx, (void *)A->ky, (void *)A->kz, (void *)A->dinv, (void *)A->r,
+                      (void *)A->p, (void *)A->q, (void *)A->part, (void *)A->st})
+        if (ptr) (void)hipFree(ptr);
+    if (A->host_st) (void)hipHostFree(A->host_st);
+    delete A;
+}
+
+extern "C" int guess_op_create(int nx, int ny, int nz, double inv_h2, double shift, const double *kappa,
+                               guess_op_t *out) {
+    if (!out) return fail(GUESS_EINVAL, "guess_op_create: out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(GUESS_EINVAL, "guess_op_create: grid sizes must be >= 1");
+    if (!(inv_h2 > 0.0) || !(shift >= 0.0) || !std::isfinite(inv_h2) || !std::isfinite(shift))
+        return fail(GUESS_EINVAL, "guess_op_create: need inv_h2 > 0 and shift >= 0");
+    const int64_t n = (int64_t)nx * ny * nz;
+    if (n >= ((int64_t)1 << 31)) return fail(GUESS_EINVAL, "guess_op_create: grid too large (N >= 2^31)");
+    guess_op *A = new (std::nothrow) guess_op();
+    if (!A) return fail(GUESS_ENOMEM, "guess_op_create: host allocation failed");
+    A->g.nx = nx;
+    A->g.ny = ny;
+    A->g.nz = nz;
+    A->g.nxy = (int64_t)nx * ny;
+    A->g.n = n;
+    A->g.c = inv_h2;
+    A->g.shift = shift;
+    A->g.dinv_const = 1.0 / (inv_h2 * 6.0 + shift);
+    auto alloc = [&](void **ptr, size_t bytes) -> int {
+        hipError_t e = hipMalloc(ptr, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(GUESS_ENOMEM, "guess_op_create: device allocation failed");
+        }
+        return GUESS_OK;
+    };
+    int rc = GUESS_OK;
+    if (rc == GUESS_OK) rc = alloc((void **)&A->r, n * 8);
+    if (rc == GUESS_OK) rc = alloc((void **)&A->p, n * 8);
+    if (rc == GUESS_OK) rc = alloc((void **)&A->q, n * 8);
+    if (rc == GUESS_OK) rc = alloc((void **)&A->part, sizeof(double) * lg::kMaxPartialBlocks * lg::kMaxDots);
+    if (rc == GUESS_OK) rc = alloc((void **)&A->st, sizeof(lg::PcgState));
+    if (rc == GUESS_OK && hipHostMalloc((void **)&A->host_st, sizeof(lg::PcgState), hipHostMallocDefault) != hipSuccess)
+        rc = fail(GUESS_ENOMEM, "guess_op_create: pinned allocation failed");
+    if (rc == GUESS_OK) {
+        lg::PcgState z{};
+        if (hipMemcpy(A->st, &z, sizeof z, hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(GUESS_EHIP, "guess_op_create: state upload failed");
+    }
+    if (rc == GUESS_OK && kappa) {
+        const int64_t nfx = (int64_t)(nx + 1) * ny * nz, nfy = (int64_t)nx * (ny + 1) * nz,
+                      nfz = (int64_t)nx * ny * (nz + 1);
+        rc = alloc((void **)&A->kx, nfx * 8);
+        if (rc == GUESS_OK) rc = alloc((void **)&A->ky, nfy * 8);
+        if (rc == GUESS_OK) rc = alloc((void **)&A->kz, nfz * 8);
+        if (rc == GUESS_OK) rc = alloc((void **)&A->dinv, n * 8);
+        if (rc == GUESS_OK) {
+            lg::launch_build_faces(A->g, kappa, A->kx, A->ky, A->kz, A->dinv, nullptr);
+            rc = check_launch("build_faces");
+            if (rc == GUESS_OK && hipDeviceSynchronize() != hipSuccess)
+                rc = fail(GUESS_EHIP, "guess_op_create: face construction failed");
+        }
+    }
+    if (rc != GUESS_OK) {
+        op_free(A);
+        return rc;
+    }
+    *out = A;
+    return GUESS_OK;
+}
+
+extern "C" void guess_op_destroy(guess_op_t A) { op_free(A); }
+
+extern "C" int guess_op_set_stream(guess_op_t A, void *stream) {
+    if (!A) return fail(GUESS_EINVAL, "guess_op_set_stream: NULL operator");
+    A->stream = (hipStream_t)stream;
+    return GUESS_OK;
+}
+
+extern "C" int64_t guess_op_size(guess_op_t A) { return A ? A->g.n : 0; }
+
+extern "C" int op_apply(guess_op_t A, const double *x, double *y) {
+    if (!A || !x || !y) return fail(GUESS_EINVAL, "op_apply: NULL argument");
+    if (x == y) return fail(GUESS_EINVAL, "op_apply: x and y must not alias");
+    lg::launch_op_apply(A->g, x, y, A->stream);
+    return check_launch("op_apply");
+}
+
+extern "C" int pcg_solve_ex(guess_op_t A, const double *b, double *x, double rtol, int maxit, int stop_rule,
+                            int *iters, double *relres) {
+    if (iters) *iters = 0;
+    if (relres) *relres = 0.0;
+    if (!A || !b || !x) return fail(GUESS_EINVAL, "pcg_solve: NULL argument");
+    if (b == x) return fail(GUESS_EINVAL, "pcg_solve: b and x must not alias");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(GUESS_EINVAL, "pcg_solve: need rtol >= 0 and maxit >= 0");
+    if (stop_rule != GUESS_STOP_RHS && stop_rule != GUESS_STOP_INITRESID)
+        return fail(GUESS_EINVAL, "pcg_solve: unknown stopping rule");
+    hipStream_t s = A->stream;
+    lg::PcgState init{};
+    init.rule = stop_rule;
+    *A->host_st = init;
+    LG_HIP(hipMemcpyAsync(A->st, A->host_st, sizeof init, hipMemcpyHostToDevice, s));
+    lg::launch_pcg_init(A->g, b, x, A->r, A->p, A->part, A->st, rtol, stop_rule, s);
+    LG_TRY(check_launch("pcg_init"));
+    auto read_state = [&]() -> int {
+        LG_HIP(hipMemcpyAsync(A->host_st, A->st, sizeof(lg::PcgState), hipMemcpyDeviceToHost, s));
+        LG_HIP(hipStreamSynchronize(s));
+        return GUESS_OK;
+    };
+    LG_TRY(read_state());
+    int launched = 0;
+    // Iterations are enqueued in batches; kernels of a batch return at once
+    // after convergence, so the count stays exact.  Batches grow with the
+    // iteration count so that short solves do not pay for long batches.
+    while (!(A->host_st->converged | A->host_st->breakdown) && launched < maxit) {
+        int chunk = launched < 4 ? 2 : (launched < 32 ? 4 : (launched < 128 ? 8 : 16));
+        if (chunk > maxit - launched) chunk = maxit - launched;
+        for (int c = 0; c < chunk; ++c) lg::launch_pcg_iter(A->g, x, A->r, A->p, A->q, A->part, A->st, s);
+        LG_TRY(check_launch("pcg_iter"));
+        launched += chunk;
+        LG_TRY(read_state());
+    }
+    const lg::PcgState &st = *A->host_st;
+    if (iters) *iters = st.it;
+    if (relres) *relres = st.bb > 0.0 ? std::sqrt(st.rr) / std::sqrt(st.bb) : std::sqrt(st.rr);
+    if (st.converged) return GUESS_OK;
+    if (st.breakdown) return fail(GUESS_EBREAKDOWN, "pcg_solve: breakdown (p^T A p <= 0 or not finite)");
+    return fail(GUESS_ENOTCONV, "pcg_solve: maxit reached");
+}
+
+extern "C" int pcg_solve(guess_op_t A, const double *b, double *x, double rtol, int maxit, int *iters,
+                         double *relres) {
+    return pcg_solve_ex(A, b, x, rtol, maxit, GUESS_STOP_RHS, iters, relres);
+}
+
+// ====================================================================== weights
+// Least-squares extrapolation weights beta = V (V^T V)^{-1} v (§3.2) with a
+// Legendre basis on the nodes t_i = -1 + (i-1) h, h = 2/(k-1), evaluated at
+// t = 1 + h.  With V = Q R (Householder), beta = Q R^{-T} v.
+extern "C" int guess_extrap_weights(int m, int k, double *beta) {
+    if (!beta) return fail(GUESS_EINVAL, "guess_extrap_weights: beta is NULL");
+    if (k < 1 || k > GUESS_MAX_M || m < 0 || m > k - 1)
+        return fail(GUESS_EINVAL, "guess_extrap_weights: need 1 <= k <= 16 and 0 <= m <= k-1");
+    if (k == 1) {
+        beta[0] = 1.0;
+        return GUESS_OK;
+    }
+    const int n = m + 1;
+    const double h = 2.0 / (k - 1);
+    double V[GUESS_MAX_M][GUESS_MAX_M];  // V[i][j] = P_j(t_i)
+    double v[GUESS_MAX_M];
+    auto legendre = [&](double t, double *P) {
+        P[0] = 1.0;
+        if (n > 1) P[1] = t;
+        for (int j = 1; j + 1 < n; ++j) P[j + 1] = ((2 * j + 1) * t * P[j] - j * P[j - 1]) / (j + 1);
+    };
+    for (int i = 0; i < k; ++i) legendre(-1.0 + i * h, V[i]);
+    legendre(1.0 + h, v);
+    // Householder QR: reflector c acts on rows c..k-1; u[c] stores its vector.
+    double u[GUESS_MAX_M][GUESS_MAX_M];
+    double R[GUESS_MAX_M][GUESS_MAX_M];
+    for (int c = 0; c < n; ++c) {
+        double nrm = 0.0;
+        for (int i = c; i < k; ++i) nrm += V[i][c] * V[i][c];
+        nrm = std::sqrt(nrm);
+        const double alpha = V[c][c] > 0 ? -nrm : nrm;
+        for (int i = 0; i < k; ++i) u[c][i] = 0.0;
+        for (int i = c; i < k; ++i) u[c][i] = V[i][c];
+        u[c][c] -= alpha;
+        double un = 0.0;
+        for (int i = c; i < k; ++i) un += u[c][i] * u[c][i];
+        un = std::sqrt(un);
+        if (un > 0)
+            for (int i = c; i < k; ++i) u[c][i] /= un;
+        for (int j = c; j < n; ++j) {
+            double dot = 0.0;
+            for (int i = c; i < k; ++i) dot += u[c][i] * V[i][j];
+            for (int i = c; i < k; ++i) V[i][j] -= 2.0 * u[c][i] * dot;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) R[i][j] = j >= i ? V[i][j] : 0.0;
+    // R^T y = v (forward substitution)
+    double z[GUESS_MAX_M];
+    for (int i = 0; i < k; ++i) z[i] = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double s = v[i];
+        for (int j = 0; j < i; ++j) s -= R[j][i] * z[j];
+        z[i] = s / R[i][i];
+    }
+    // beta = H_0 H_1 ... H_{n-1} [y; 0]
+    for (int c = n - 1; c >= 0; --c) {
+        double dot = 0.0;
+        for (int i = c; i < k; ++i) dot += u[c][i] * z[i];
+        for (int i = c; i < k; ++i) z[i] -= 2.0 * u[c][i] * dot;
+    }
+    for (int i = 0; i < k; ++i) beta[i] = z[i];
+    return GUESS_OK;
+}
+
+// ====================================================================== context
+struct guess_ctx {
+    int64_t N = 0, ld = 0;
+    int M = 1, method = GUESS_ZERO, degree = 0, dtype = GUESS_F64, es = 8;
+    double eps_rel = 1e-6;
+    guess_op_t op = nullptr;
+    hipStream_t stream = nullptr;
+    // extrapolation ring
+    void *ring = nullptr;
+    int count = 0, head = 0;
+    double beta[GUESS_MAX_M + 1][GUESS_MAX_M][GUESS_MAX_M] = {};  // [k][m][i]
+    bool have_beta[GUESS_MAX_M + 1][GUESS_MAX_M] = {};
+    // projection
+    void *X = nullptr, *B = nullptr;
+    double *w = nullptr, *part = nullptr;
+    lg::ProjState *st = nullptr, *host_st = nullptr;
+    int last_update_ax = 0;
+    // bookkeeping
+    double form_bytes = 0.0, update_bytes = 0.0;
+    // optional per-kernel timing of the most recent form / update call
+    bool prof = false;
+    lg::KEvents kev{};
+};
+
+static void ctx_free(guess_ctx *g) {
+    if (!g) return;
+    if (g->prof)
+        for (hipEvent_t e : g->kev.e) (void)hipEventDestroy(e);
+    for (void *ptr : {g->ring, g->X, g->B, (void *)g->w, (void *)g->part, (void *)g->st})
+        if (ptr) (void)hipFree(ptr);
+    if (g->host_st) (void)hipHostFree(g->host_st);
+    delete g;
+}
+
+extern "C" size_t guess_workspace_bytes(int64_t N, int M, int method, int dtype) {
+    const int es = esize(dtype);
+    if (N < 1 || M < 1 || es == 0) return 0;
+    const size_t col = (size_t)col_stride(N) * es;
+    switch (method) {
+        case GUESS_LAST: return col;
+        case GUESS_EXTRAP: return col * M;
+        case GUESS_PROJ:
+            return 2 * col * M + (size_t)N * 8 + sizeof(double) * lg::kMaxPartialBlocks * lg::kMaxDots +
+                   sizeof(lg::ProjState);
+    }
+    return 0;
+}
+
+static int proj_upload_state(guess_ctx *g) {
+    lg::ProjState s{};
+    s.M = g->M;
+    s.eps_rel = g->eps_rel;
+    *g->host_st = s;
+    LG_HIP(hipMemcpyAsync(g->st, g->host_st, sizeof s, hipMemcpyHostToDevice, g->stream));
+    LG_HIP(hipStreamSynchronize(g->stream));
+    return GUESS_OK;
+}
+
+extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
+    if (!o || !out) return fail(GUESS_EINVAL, "guess_create_ex: NULL argument");
+    *out = nullptr;
+    int M = o->M;
+    if (o->method == GUESS_LAST) M = 1;
+    if (o->N < 1) return fail(GUESS_EINVAL, "guess_create: need N >= 1");
+    if (o->method < GUESS_ZERO || o->method > GUESS_PROJ) return fail(GUESS_EINVAL, "guess_create: unknown method");
+    if (o->method != GUESS_ZERO && (M < 1 || M > GUESS_MAX_M))
+        return fail(GUESS_EINVAL, "guess_create: need 1 <= M <= 16");
+    const int degree = o->method == GUESS_LAST ? 0 : o->degree;
+    if (o->method == GUESS_EXTRAP && (degree < 0 || degree > M - 1))
+        return fail(GUESS_EINVAL, "guess_create: need 0 <= degree <= M-1");
+    if (esize(o->dtype) == 0) return fail(GUESS_EINVAL, "guess_create: unknown dtype");
+    if (o->op && o->op->g.n != o->N) return fail(GUESS_EINVAL, "guess_create: operator size differs from N");
+    guess_ctx *g = new (std::nothrow) guess_ctx();
+    if (!g) return fail(GUESS_ENOMEM, "guess_create: host allocation failed");
+    g->N = o->N;
+    g->ld = col_stride(o->N);
+    g->M = o->method == GUESS_ZERO ? 0 : M;
+    g->method = o->method;
+    g->degree = degree;
+    g->dtype = o->dtype;
+    g->es = esize(o->dtype);
+    g->eps_rel = o->eps_rel > 0.0 ? o->eps_rel : 1e-6;
+    g->op = o->op;
+    g->stream = (hipStream_t)o->stream;
+    const size_t col = (size_t)g->ld * g->es;
+    auto alloc = [&](void **ptr, size_t bytes) -> int {
+        hipError_t e = hipMalloc(ptr, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(GUESS_ENOMEM, "guess_create: device allocation of " + std::to_string(bytes) +
+                                          " bytes failed");
+        }
+        return GUESS_OK;
+    };
+    int rc = GUESS_OK;
+    if (g->method == GUESS_EXTRAP || g->method == GUESS_LAST) {
+        rc = alloc(&g->ring, col * g->M);
+    } else if (g->method == GUESS_PROJ) {
+        rc = alloc(&g->X, col * g->M);
+        if (rc == GUESS_OK) rc = alloc(&g->B, col * g->M);
+        if (rc == GUESS_OK) rc = alloc((void **)&g->w, (size_t)g->N * 8);
+        if (rc == GUESS_OK) rc = alloc((void **)&g->part, sizeof(double) * lg::kMaxPartialBlocks * lg::kMaxDots);
+        if (rc == GUESS_OK) rc = alloc((void **)&g->st, sizeof(lg::ProjState));
+        if (rc == GUESS_OK && hipHostMalloc((void **)&g->host_st, sizeof(lg::ProjState), hipHostMallocDefault) != hipSuccess)
+            rc = fail(GUESS_ENOMEM, "guess_create: pinned allocation failed");
+        if (rc == GUESS_OK) rc = proj_upload_state(g);
+    }
+    if (rc != GUESS_OK) {
+        ctx_free(g);
+        return rc;
+    }
+    *out = g;
+    return GUESS_OK;
+}
+
+extern "C" guess_t guess_create(int64_t N, int M, int method, int degree) {
+    guess_opts o{};
+    o.N = N;
+    o.M = M;
+    o.method = method;
+    o.degree = degree;
+    o.dtype = GUESS_F64;
+    o.eps_rel = 1e-6;
+    guess_t g = nullptr;
+    if (guess_create_ex(&o, &g) != GUESS_OK) return nullptr;
+    return g;
+}
+
+extern "C" void guess_destroy(guess_t g) { ctx_free(g); }
+
+extern "C" int guess_set_stream(guess_t g, void *stream) {
+    if (!g) return fail(GUESS_EINVAL, "guess_set_stream: NULL context");
+    g->stream = (hipStream_t)stream;
+    return GUESS_OK;
+}
+
+extern "C" int guess_set_op(guess_t g, guess_op_t A) {
+    if (!g) return fail(GUESS_EINVAL, "guess_set_op: NULL context");
+    if (A && A->g.n != g->N) return fail(GUESS_EINVAL, "guess_set_op: operator size differs from N");
+    g->op = A;
+    return GUESS_OK;
+}
+
+static int ring_weights(guess_ctx *g, int m, int k, const double **out) {
+    if (!g->have_beta[k][m]) {
+        LG_TRY(guess_extrap_weights(m, k, g->beta[k][m]));
+        g->have_beta[k][m] = true;
+    }
+    *out = g->beta[k][m];
+    return GUESS_OK;
+}
+
+static lg::ProjBufs proj_bufs(guess_ctx *g) {
+    lg::ProjBufs p;
+    p.X = g->X;
+    p.B = g->B;
+    p.w = g->w;
+    p.part = g->part;
+    p.st = g->st;
+    p.N = g->N;
+    p.ld = g->ld;
+    p.M = g->M;
+    p.dtype = g->dtype;
+    return p;
+}
+
+extern "C" int guess_form(guess_t g, const double *b, double *x0) {
+    if (!g || !x0) return fail(GUESS_EINVAL, "guess_form: NULL argument");
+    g->kev.count = 0;
+    if (!aligned16(x0)) return fail(GUESS_EINVAL, "guess_form: x0 must be 16-byte aligned");
+    const int64_t N = g->N;
+    switch (g->method) {
+        case GUESS_ZERO:
+            lg::launch_fill_zero(x0, N, g->stream);
+            g->form_bytes = 8.0 * N;
+            return check_launch("guess_form");
+        case GUESS_LAST:
+        case GUESS_EXTRAP: {
+            const int k = g->count;
+            if (k == 0) {
+                lg::launch_fill_zero(x0, N, g->stream);
+                g->form_bytes = 8.0 * N;
+                return check_launch("guess_form");
+            }
+            const int m = g->degree < k - 1 ? g->degree : k - 1;
+            const double *beta;
+            LG_TRY(ring_weights(g, m, k, &beta));
+            const void *slots[GUESS_MAX_M];
+            const int oldest = ((g->head - k) % g->M + g->M) % g->M;
+            for (int j = 0; j < k; ++j)
+                slots[j] = (const char *)g->ring + (size_t)((oldest + j) % g->M) * g->ld * g->es;
+            LG_TRY(lg::launch_extrap_form(g->dtype, k, slots, beta, x0, N, g->stream, g->prof ? &g->kev : nullptr));
+            g->form_bytes = (double)N * (k * g->es + 8);
+            return check_launch("guess_form");
+        }
+        case GUESS_PROJ: {
+            if (!b) return fail(GUESS_EINVAL, "guess_form: projection needs b");
+            if (b == x0) return fail(GUESS_EINVAL, "guess_form: b and x0 must not alias");
+            if (!aligned16(b)) return fail(GUESS_EINVAL, "guess_form: b must be 16-byte aligned");
+            LG_TRY(lg::launch_proj_form(proj_bufs(g), b, x0, g->stream, g->prof ? &g->kev : nullptr));
+            g->form_bytes = -1.0;  // known after the device reports d
+            return check_launch("guess_form");
+        }
+    }
+    return fail(GUESS_EINVAL, "guess_form: bad method");
+}
+
+extern "C" int guess_update(guess_t g, const double *x, const double *Ax) {
+    if (!g || !x) return fail(GUESS_EINVAL, "guess_update: NULL argument");
+    g->kev.count = 0;
+    if (!aligned16(x) || (Ax && !aligned16(Ax))) return fail(GUESS_EINVAL, "guess_update: vectors must be 16-byte aligned");
+    const int64_t N = g->N;
+    switch (g->method) {
+        case GUESS_ZERO:
+            g->update_bytes = 0.0;
+            return GUESS_OK;
+        case GUESS_LAST:
+        case GUESS_EXTRAP: {
+            void *slot = (char *)g->ring + (size_t)g->head * g->ld * g->es;
+            LG_TRY(lg::launch_ring_store(g->dtype, x, slot, N, g->stream, g->prof ? &g->kev : nullptr));
+            g->head = (g->head + 1) % g->M;
+            if (g->count < g->M) ++g->count;
+            g->update_bytes = (double)N * (8 + g->es);
+            return check_launch("guess_update");
+        }
+        case GUESS_PROJ: {
+            if (!Ax && !g->op) return fail(GUESS_EINVAL, "guess_update: projection needs Ax or an operator");
+            if (Ax == x) return fail(GUESS_EINVAL, "guess_update: Ax must not alias x");
+            LG_TRY(lg::launch_proj_update(proj_bufs(g), g->op ? &g->op->g : nullptr, x, Ax, g->stream,
+                                          g->prof ? &g->kev : nullptr));
+            g->last_update_ax = Ax != nullptr;
+            g->update_bytes = -1.0;
+            return check_launch("guess_update");
+        }
+    }
+    return fail(GUESS_EINVAL, "guess_update: bad method");
+}
+
+extern "C" int guess_get_info(guess_t g, guess_info *info) {
+    if (!g || !info) return fail(GUESS_EINVAL, "guess_get_info: NULL argument");
+    std::memset(info, 0, sizeof *info);
+    info->N = g->N;
+    info->method = g->method;
+    info->dtype = g->dtype;
+    info->M = g->M;
+    info->degree = g->degree;
+    info->form_bytes = g->form_bytes;
+    info->update_bytes = g->update_bytes;
+    if (g->method == GUESS_PROJ) {
+        LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));
+        LG_HIP(hipStreamSynchronize(g->stream));
+        const lg::ProjState &s = *g->host_st;
+        info->count = s.d;
+        info->last_accepted = s.last_accepted;
+        info->restarts = s.restarts;
+        info->rejects = s.rejects;
+        info->nonfinite = s.nonfinite;
+        info->nu = s.nu;
+        info->nu0 = s.nu0;
+        const double N = (double)g->N, es = g->es;
+        if (g->form_bytes < 0) info->form_bytes = 2.0 * N * (s.form_d * es + 8.0) - (s.form_d == 0 ? N * 8.0 : 0.0);
+        if (g->update_bytes < 0) {
+            const int d = s.upd_d;
+            if (d == 0 || d >= g->M) info->update_bytes = N * (8.0 + 2.0 * es + (g->last_update_ax ? 8.0 : 0.0));
+            else info->update_bytes = N * (5.0 * d * es + 2.0 * es + 40.0);
+        }
+    } else {
+        LG_HIP(hipStreamSynchronize(g->stream));
+        info->count = g->count;
+        info->head = g->head;
+    }
+    return GUESS_OK;
+}
+
+extern "C" int guess_reset(guess_t g) {
+    if (!g) return fail(GUESS_EINVAL, "guess_reset: NULL context");
+    g->count = 0;
+    g->head = 0;
+    if (g->method == GUESS_PROJ) {
+        LG_HIP(hipStreamSynchronize(g->stream));
+        LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));
+        LG_HIP(hipStreamSynchronize(g->stream));
+        g->host_st->d = 0;
+        g->host_st->mode = 0;
+        LG_HIP(hipMemcpyAsync(g->st, g->host_st, sizeof(lg::ProjState), hipMemcpyHostToDevice, g->stream));
+        LG_HIP(hipStreamSynchronize(g->stream));
+    }
+    return GUESS_OK;
+}
+
+extern "C" int guess_profile(guess_t g, int enable) {
+    if (!g) return fail(GUESS_EINVAL, "guess_profile: NULL context");
+    if (enable && !g->prof) {
+        for (hipEvent_t &e : g->kev.e) LG_HIP(hipEventCreate(&e));
+        g->prof = true;
+    } else if (!enable && g->prof) {
+        LG_HIP(hipStreamSynchronize(g->stream));
+        for (hipEvent_t &e : g->kev.e) (void)hipEventDestroy(e);
+        g->prof = false;
+    }
+    g->kev.count = 0;
+    return GUESS_OK;
+}
+
+extern "C" int guess_kernel_times(guess_t g, double *ms, int max, int *n) {
+    if (!g || !n || (max > 0 && !ms)) return fail(GUESS_EINVAL, "guess_kernel_times: NULL argument");
+    *n = 0;
+    if (!g->prof || g->kev.count == 0) return GUESS_OK;
+    const int cnt = g->kev.count;
+    LG_HIP(hipEventSynchronize(g->kev.e[cnt]));
+    for (int i = 0; i < cnt && i < max; ++i) {
+        float t = 0.0f;
+        LG_HIP(hipEventElapsedTime(&t, g->kev.e[i], g->kev.e[i + 1]));
+        ms[i] = t;
+    }
+    *n = cnt < max ? cnt : max;
+    return GUESS_OK;
+}
+
+extern "C" int guess_history_get(guess_t g, int which, int j, double *out) {
+    if (!g || !out) return fail(GUESS_EINVAL, "guess_history_get: NULL argument");
+    if (g->method == GUESS_EXTRAP || g->method == GUESS_LAST) {
+        if (j < 0 || j >= g->count) return fail(GUESS_EINVAL, "guess_history_get: index out of range");
+        const int oldest = ((g->head - g->count) % g->M + g->M) % g->M;
+        const void *src = (const char *)g->ring + (size_t)((oldest + j) % g->M) * g->ld * g->es;
+        LG_TRY(lg::launch_widen(g->dtype, src, 1.0, out, g->N, g->stream));
+    } else if (g->method == GUESS_PROJ) {
+        LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));
+        LG_HIP(hipStreamSynchronize(g->stream));
+        if (j < 0 || j >= g->host_st->d || (which != 0 && which != 1))
+            return fail(GUESS_EINVAL, "guess_history_get: index out of range");
+        const void *base = which == 0 ? g->X : g->B;
+        const void *src = (const char *)base + (size_t)j * g->ld * g->es;
+        LG_TRY(lg::launch_widen(g->dtype, src, g->host_st->scale[j], out, g->N, g->stream));
+    } else {
+        return fail(GUESS_EINVAL, "guess_history_get: no history for this method");
+    }
+    LG_TRY(check_launch("guess_history_get"));
+    LG_HIP(hipStreamSynchronize(g->stream));
+    return GUESS_OK;
+}
+
+// ====================================================================== workload
+namespace {
+struct PlaneWaveTables {
+    int n = -1, K = -1;
+    std::vector<int> kvec;
+    std::vector<double> theta;
+    double *dev = nullptr;  // 3 tables of K*n complex values
+};
+thread_local PlaneWaveTables g_pw;
+}  // namespace
+
+extern "C" int workload_plane_wave_rhs(int n, int K, const int *kvec, const double *theta, const double *amp,
+                                       double *b, void *stream) {
+    if (n < 1 || K < 1 || K > 64 || !kvec || !theta || !amp || !b)
+        return fail(GUESS_EINVAL, "workload_plane_wave_rhs: bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    const bool same = g_pw.dev && g_pw.n == n && g_pw.K == K &&
+                      std::equal(kvec, kvec + 3 * K, g_pw.kvec.begin()) &&
+                      std::equal(theta, theta + K, g_pw.theta.begin());
+    if (!same) {
+        if (g_pw.dev) {
+            LG_HIP(hipStreamSynchronize(s));
+            (void)hipFree(g_pw.dev);
+            g_pw.dev = nullptr;
+        }
+        std::vector<double> tab((size_t)3 * K * n * 2);
+        const double two_pi = 2.0 * M_PI, h = 1.0 / (n + 1);
+        for (int axis = 0; axis < 3; ++axis)
+            for (int k = 0; k < K; ++k)
+                for (int i = 0; i < n; ++i) {
+                    double ph = two_pi * kvec[3 * k + axis] * ((i + 1) * h);
+                    if (axis == 0) ph += theta[k];
+                    const size_t o = (((size_t)axis * K + k) * n + i) * 2;
+                    tab[o] = std::cos(ph);
+                    tab[o + 1] = std::sin(ph);
+                }
+        if (hipMalloc((void **)&g_pw.dev, tab.size() * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            g_pw.dev = nullptr;
+            return fail(GUESS_ENOMEM, "workload_plane_wave_rhs: allocation failed");
+        }
+        LG_HIP(hipMemcpy(g_pw.dev, tab.data(), tab.size() * 8, hipMemcpyHostToDevice));
+        g_pw.n = n;
+        g_pw.K = K;
+        g_pw.kvec.assign(kvec, kvec + 3 * K);
+        g_pw.theta.assign(theta, theta + K);
+    }
+    const size_t tsz = (size_t)K * n * 2;
+    LG_TRY(lg::launch_plane_wave_rhs(n, K, g_pw.dev, g_pw.dev + tsz, g_pw.dev + 2 * tsz, amp, b, s));
+    return check_launch("workload_plane_wave_rhs");
+}
+
+// ====================================================================== vectors
+namespace {
+struct VecScratch {
+    double *part = nullptr, *out = nullptr;
+};
+thread_local VecScratch g_vec;
+}  // namespace
+
+extern "C" int vec_multidot(int64_t N, int K, const double *V, const double *y, double *out, void *stream) {
+    if (N < 1 || K < 1 || K > 64 || !V || !y || !out) return fail(GUESS_EINVAL, "vec_multidot: bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (!g_vec.part) {
+        if (hipMalloc((void **)&g_vec.part, sizeof(double) * lg::kMaxPartialBlocks * 8) != hipSuccess ||
+            hipMalloc((void **)&g_vec.out, sizeof(double) * 64) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(GUESS_ENOMEM, "vec_multidot: allocation failed");
+        }
+    }
+    LG_TRY(lg::launch_multidot(N, K, V, y, g_vec.part, nullptr, g_vec.out, s));
+    LG_TRY(check_launch("vec_multidot"));
+    LG_HIP(hipMemcpyAsync(out, g_vec.out, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+    LG_HIP(hipStreamSynchronize(s));
+    return GUESS_OK;
+}
+
+extern "C" int vec_combine(int64_t N, int K, const double *V, const double *c, double *y, void *stream) {
+    if (N < 1 || K < 1 || K > 64 || !V || !c || !y) return fail(GUESS_EINVAL, "vec_combine: bad argument");
+    LG_TRY(lg::launch_combine(N, K, V, c, y, (hipStream_t)stream));
+    return check_launch("vec_combine");
+}
+
+extern "C" int guess_copy_kernel(void *dst, const void *src, size_t bytes, void *stream) {
+    if (!dst || !src) return fail(GUESS_EINVAL, "guess_copy_kernel: NULL argument");
+    if (!aligned16(dst) || !aligned16(src)) return fail(GUESS_EINVAL, "guess_copy_kernel: need 16-byte alignment");
+    LG_TRY(lg::launch_copy(dst, src, bytes, (hipStream_t)stream));
+    return check_launch("guess_copy_kernel");
+}
+
+// ====================================================================== errors
+extern "C" const char *guess_strerror(int code) {
+    switch (code) {
+        case GUESS_OK: return "success";
+        case GUESS_EINVAL: return "invalid argument";
+        case GUESS_ENOMEM: return "out of device memory";
+        case GUESS_EHIP: return "HIP runtime error";
+        case GUESS_ENOTCONV: return "PCG did not converge within maxit";
+        case GUESS_EBREAKDOWN: return "PCG breakdown";
+        case GUESS_ENONFINITE: return "non-finite value";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *guess_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,97 @@
+// Host-side launchers of the libguess kernels (one translation unit per family).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "libguess.h"
+#include "stencil.h"
+
+namespace lg {
+
+// Optional per-kernel timing: when non-null, a launcher records e[i] before
+// its i-th kernel and e[count] after the last one (on the launch stream).
+struct KEvents {
+    hipEvent_t e[8];
+    int count;          // kernels launched (set by the launcher)
+};
+inline void kev(KEvents *k, int i, hipStream_t s) {
+    if (k) (void)hipEventRecord(k->e[i], s);
+}
+
+// Device-resident state of a projection history.  Decisions (restart,
+// accept / reject) are taken on the device, so a sequence of guess_form /
+// guess_update calls never waits for the host.
+struct ProjState {
+    int d;                  // columns in the history
+    int mode;               // 1 while the current update is a restart
+    int last_accepted;
+    int restarts;
+    int rejects;
+    int nonfinite;          // sticky
+    int M;
+    int form_d;             // columns used by the last guess (written by proj_combine)
+    int upd_d;              // columns at the start of the last update (written by proj_apply)
+    int pad;
+    unsigned int ticket[4]; // last-workgroup counters of the reduction kernels
+    double eps_rel;
+    double nu0sq, nusq, nu0, nu;
+    double scale[GUESS_MAX_M];   // column j of X (and B) = scale[j] * stored column j
+    double gamma[GUESS_MAX_M];   // guess: x0 = sum_j gamma[j] * stored X_j
+    double c[GUESS_MAX_M];       // update: Gram-Schmidt coefficients (A inner product)
+    double cs[GUESS_MAX_M];      // update: c[j] * scale[j]
+};
+
+// Device-resident state of a PCG solve.
+struct PcgState {
+    double rho, alpha, beta, rr, bb, rr0, thresh;
+    int it, converged, breakdown, rule;
+    unsigned int ticket[4];
+};
+
+// ---- extrapolation (extrap.hip)
+int launch_extrap_form(int dtype, int k, const void *const *slots, const double *beta,
+                       double *x0, int64_t N, hipStream_t s, KEvents *ev = nullptr);
+int launch_ring_store(int dtype, const double *x, void *slot, int64_t N, hipStream_t s,
+                      KEvents *ev = nullptr);
+int launch_fill_zero(double *x, int64_t N, hipStream_t s);
+int launch_widen(int dtype, const void *src, double scale, double *out, int64_t N, hipStream_t s);
+
+// ---- projection (proj.hip)
+struct ProjBufs {
+    void *X;                 // M stored columns of X, each N elements of the storage type
+    void *B;                 // M stored columns of B = A X
+    double *w;               // FP64 scratch N (A x of the current update)
+    double *part;            // per-workgroup partial sums
+    ProjState *st;           // device state
+    int64_t N, ld;           // ld: elements between consecutive columns
+    int M, dtype;
+};
+int launch_proj_form(const ProjBufs &p, const double *b, double *x0, hipStream_t s,
+                     KEvents *ev = nullptr);
+int launch_proj_update(const ProjBufs &p, const Grid *g, const double *x, const double *Ax,
+                       hipStream_t s, KEvents *ev = nullptr);
+
+// ---- operator and PCG (op.hip)
+int launch_build_faces(Grid &g, const double *kappa, double *kx, double *ky, double *kz,
+                       double *dinv, hipStream_t s);
+int launch_op_apply(const Grid &g, const double *x, double *y, hipStream_t s);
+int launch_pcg_init(const Grid &g, const double *b, const double *x, double *r, double *p,
+                    double *part, PcgState *st, double rtol, int rule, hipStream_t s);
+int launch_pcg_iter(const Grid &g, double *x, double *r, double *p, double *q, double *part,
+                    PcgState *st, hipStream_t s);
+int pcg_grid(const Grid &g);
+
+// ---- vectors and workload (vec.hip)
+int launch_multidot(int64_t N, int K, const double *V, const double *y, double *part,
+                    unsigned int *ticket, double *out_dev, hipStream_t s);
+int launch_combine(int64_t N, int K, const double *V, const double *c, double *y, hipStream_t s);
+int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+int launch_plane_wave_rhs(int n, int K, const double *tabx, const double *taby,
+                          const double *tabz, const double *amp, double *b, hipStream_t s);
+
+// grid-size knob for the streaming kernels (LIBGUESS_GRID_CAP, default below)
+int grid_cap();
+int reduce_blocks();
+
+}  // namespace lg

@@ -1,0 +1,137 @@
+// Generic FP64 vector kernels (multi-dot, combination, copy) and the
+// plane-wave right-hand-side generator of the synthetic workloads.
+#include "common.h"
+#include "launch.h"
+
+namespace lg {
+
+constexpr int kMaxVecK = 64;
+
+struct CombArgs {
+    double c[kMaxVecK];
+};
+
+// out[k] = <V_k, y> for K <= 64 vectors, 8 at a time so that the
+// accumulators stay in registers; deterministic two-stage reduction (partial
+// sums per workgroup, then one workgroup sums them in a fixed order).
+__global__ __launch_bounds__(kBlock) void multidot8_kernel(int64_t N, int K0, int KN,
+                                                           const double *__restrict__ V,
+                                                           const double *__restrict__ y, double *part) {
+    // partial sums of up to 8 dot products (vectors K0 .. K0+KN-1) per workgroup
+    double acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N; t += stride) {
+        const double yt = y[t];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (k < KN) acc[k] = __builtin_fma(V[(int64_t)(K0 + k) * N + t], yt, acc[k]);
+    }
+    __shared__ double lds[kLdsDoubles];
+    block_partials<8>(acc, part, lds);
+}
+
+__global__ __launch_bounds__(kBlock) void multidot_final_kernel(int nb, int K0, int KN, const double *part,
+                                                                double *out) {
+    __shared__ double lds[kLdsDoubles];
+    double tot[8];
+    final_sums<8>(part, nb, tot, lds);
+    if (threadIdx.x < KN) out[K0 + threadIdx.x] = tot[threadIdx.x];
+}
+
+int launch_multidot(int64_t N, int K, const double *V, const double *y, double *part, unsigned int *ticket,
+                    double *out_dev, hipStream_t s) {
+    (void)ticket;
+    if (K < 1 || K > kMaxVecK) return GUESS_EINVAL;
+    const int gr = stream_grid(N, reduce_blocks());
+    for (int k0 = 0; k0 < K; k0 += 8) {
+        const int kn = K - k0 < 8 ? K - k0 : 8;
+        multidot8_kernel<<<gr, kBlock, 0, s>>>(N, k0, kn, V, y, part);
+        multidot_final_kernel<<<1, kBlock, 0, s>>>(gr, k0, kn, part, out_dev);
+    }
+    return GUESS_OK;
+}
+
+__global__ __launch_bounds__(kBlock) void combine_kernel(int64_t N, int K, const double *__restrict__ V,
+                                                         CombArgs a, double *__restrict__ y) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < N; t += stride) {
+        double acc = a.c[0] * V[t];
+        for (int k = 1; k < K; ++k) acc = __builtin_fma(a.c[k], V[(int64_t)k * N + t], acc);
+        y[t] = acc;
+    }
+}
+
+int launch_combine(int64_t N, int K, const double *V, const double *c, double *y, hipStream_t s) {
+    if (K < 1 || K > kMaxVecK) return GUESS_EINVAL;
+    CombArgs a{};
+    for (int k = 0; k < K; ++k) a.c[k] = c[k];
+    combine_kernel<<<stream_grid(N, grid_cap()), kBlock, 0, s>>>(N, K, V, a, y);
+    return GUESS_OK;
+}
+
+// Plain copy with 16-byte accesses (the roofline reference kernel).
+__global__ __launch_bounds__(kBlock) void copy_kernel(const d2 *__restrict__ src, d2 *__restrict__ dst,
+                                                      int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n16; t += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + t), dst + t);
+}
+
+__global__ void copy_tail_kernel(const unsigned char *src, unsigned char *dst, int64_t off, int64_t n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) dst[off + t] = src[off + t];
+}
+
+int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 > 0)
+        copy_kernel<<<stream_grid(n16, grid_cap()), kBlock, 0, s>>>((const d2 *)src, (d2 *)dst, n16);
+    const int64_t tail = (int64_t)(bytes - (size_t)n16 * 16);
+    if (tail > 0)
+        copy_tail_kernel<<<1, 64, 0, s>>>((const unsigned char *)src, (unsigned char *)dst, n16 * 16, tail);
+    return GUESS_OK;
+}
+
+// b_i = sum_k amp_k Re(ex_k(i) ey_k(j) ez_k(l)) with per-axis complex tables
+// ex_k(i) = exp(1i (2 pi kx_k x_i + theta_k)), ey_k(j) = exp(1i 2 pi ky_k y_j),
+// ez_k(l) = exp(1i 2 pi kz_k z_l); tables are laid out [k][i] (re, im).
+struct AmpArgs {
+    double a[kMaxVecK];
+};
+
+__global__ __launch_bounds__(kBlock) void plane_wave_kernel(int n, int K, const d2 *__restrict__ tx,
+                                                            const d2 *__restrict__ ty,
+                                                            const d2 *__restrict__ tz, AmpArgs amp,
+                                                            double *__restrict__ b) {
+    const int64_t N = (int64_t)n * n * n;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+        const int i = (int)(p % n);
+        const int j = (int)((p / n) % n);
+        const int l = (int)(p / ((int64_t)n * n));
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const d2 ex = tx[(int64_t)k * n + i], ey = ty[(int64_t)k * n + j], ez = tz[(int64_t)k * n + l];
+            const double ur = ex.x * ey.x - ex.y * ey.y;
+            const double ui = ex.x * ey.y + ex.y * ey.x;
+            const double re = ur * ez.x - ui * ez.y;
+            acc = __builtin_fma(amp.a[k], re, acc);
+        }
+        b[p] = acc;
+    }
+}
+
+int launch_plane_wave_rhs(int n, int K, const double *tabx, const double *taby, const double *tabz,
+                          const double *amp, double *b, hipStream_t s) {
+    if (K < 1 || K > kMaxVecK) return GUESS_EINVAL;
+    AmpArgs a{};
+    for (int k = 0; k < K; ++k) a.a[k] = amp[k];
+    const int64_t N = (int64_t)n * n * n;
+    plane_wave_kernel<<<stream_grid(N, grid_cap()), kBlock, 0, s>>>(n, K, (const d2 *)tabx, (const d2 *)taby,
+                                                                    (const d2 *)tabz, a, b);
+    return GUESS_OK;
+}
+
+}  // namespace lg

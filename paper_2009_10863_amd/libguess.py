@@ -1,0 +1,272 @@
+"""ctypes binding of the libguess C ABI (``include/libguess.h``).
+
+Argument marshalling only: every function below forwards to the entry point
+of the same name in ``libguess.so``; all arithmetic runs in the library's HIP
+kernels.  Vector arguments may be raw device addresses (int) or torch CUDA
+tensors of dtype float64 (their ``data_ptr()`` is passed).  Errors raise
+``GuessError`` with the library's message.  Importing this module fails
+loudly when the shared library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libguess.so")
+
+# ---------------------------------------------------------------- constants
+ZERO, LAST, EXTRAP, PROJ = 0, 1, 2, 3
+F64, F32, F16, BF16 = 0, 1, 2, 3
+OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+STOP_RHS, STOP_INITRESID = 0, 1
+MAX_M = 16
+METHODS = {"zero": ZERO, "last": LAST, "extrap": EXTRAP, "proj": PROJ}
+DTYPES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
+ELEM_BYTES = {F64: 8, F32: 4, F16: 2, BF16: 2}
+
+
+class GuessError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libguess error {code}: {msg}")
+        self.code = code
+
+
+class guess_opts(C.Structure):
+    _fields_ = [("N", C.c_int64), ("M", C.c_int), ("method", C.c_int), ("degree", C.c_int),
+                ("dtype", C.c_int), ("eps_rel", C.c_double), ("op", C.c_void_p),
+                ("stream", C.c_void_p)]
+
+
+class guess_info(C.Structure):
+    _fields_ = [("N", C.c_int64), ("method", C.c_int), ("dtype", C.c_int), ("M", C.c_int),
+                ("degree", C.c_int), ("count", C.c_int), ("head", C.c_int),
+                ("last_accepted", C.c_int), ("restarts", C.c_int), ("rejects", C.c_int),
+                ("nonfinite", C.c_int), ("nu", C.c_double), ("nu0", C.c_double),
+                ("form_bytes", C.c_double), ("update_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libguess.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    P, I, I64, D, S = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_size_t
+    sig = {
+        "guess_op_create": (I, [I, I, I, D, D, P, C.POINTER(P)]),
+        "guess_op_destroy": (None, [P]),
+        "guess_op_set_stream": (I, [P, P]),
+        "guess_op_size": (I64, [P]),
+        "op_apply": (I, [P, P, P]),
+        "pcg_solve": (I, [P, P, P, D, I, C.POINTER(I), C.POINTER(D)]),
+        "pcg_solve_ex": (I, [P, P, P, D, I, I, C.POINTER(I), C.POINTER(D)]),
+        "guess_create": (P, [I64, I, I, I]),
+        "guess_create_ex": (I, [C.POINTER(guess_opts), C.POINTER(P)]),
+        "guess_destroy": (None, [P]),
+        "guess_set_stream": (I, [P, P]),
+        "guess_set_op": (I, [P, P]),
+        "guess_workspace_bytes": (S, [I64, I, I, I]),
+        "guess_form": (I, [P, P, P]),
+        "guess_update": (I, [P, P, P]),
+        "guess_get_info": (I, [P, C.POINTER(guess_info)]),
+        "guess_reset": (I, [P]),
+        "guess_extrap_weights": (I, [I, I, C.POINTER(D)]),
+        "guess_history_get": (I, [P, I, I, P]),
+        "workload_plane_wave_rhs": (I, [I, I, C.POINTER(I), C.POINTER(D), C.POINTER(D), P, P]),
+        "vec_multidot": (I, [I64, I, P, P, C.POINTER(D), P]),
+        "vec_combine": (I, [I64, I, P, C.POINTER(D), P, P]),
+        "guess_strerror": (C.c_char_p, [I]),
+        "guess_last_error": (C.c_char_p, []),
+        "guess_copy_kernel": (I, [P, P, S, P]),
+        "guess_profile": (I, [P, I]),
+        "guess_kernel_times": (I, [P, C.POINTER(D), I, C.POINTER(I)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTED = (
+    "guess_op_create", "guess_op_destroy", "guess_op_set_stream", "guess_op_size", "op_apply",
+    "pcg_solve", "pcg_solve_ex", "guess_create", "guess_create_ex", "guess_destroy",
+    "guess_set_stream", "guess_set_op", "guess_workspace_bytes", "guess_form", "guess_update",
+    "guess_get_info", "guess_reset", "guess_extrap_weights", "guess_history_get",
+    "workload_plane_wave_rhs", "vec_multidot", "vec_combine", "guess_strerror",
+    "guess_last_error", "guess_copy_kernel", "guess_profile", "guess_kernel_times",
+)
+
+
+def lib():
+    return _lib
+
+
+def _check(code):
+    if code != OK:
+        raise GuessError(code, _lib.guess_last_error().decode() or _lib.guess_strerror(code).decode())
+    return code
+
+
+def addr(v) -> int:
+    """Device address of a vector argument (int, None, or torch tensor)."""
+    if v is None:
+        return None
+    if isinstance(v, int):
+        return v
+    import torch
+
+    if not isinstance(v, torch.Tensor):
+        raise TypeError("expected a device address or a torch tensor")
+    if not v.is_cuda:
+        raise ValueError("libguess needs device (HIP) tensors")
+    if not v.is_contiguous():
+        raise ValueError("libguess needs contiguous tensors")
+    return v.data_ptr()
+
+
+def stream_handle(stream=None):
+    """hipStream_t of a torch stream (default: torch's current stream)."""
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+# ---------------------------------------------------------------- operator
+def guess_op_create(nx, ny, nz, inv_h2, shift, kappa=None) -> int:
+    out = C.c_void_p()
+    _check(_lib.guess_op_create(nx, ny, nz, inv_h2, shift, addr(kappa), C.byref(out)))
+    return out.value
+
+
+def guess_op_destroy(A) -> None:
+    _lib.guess_op_destroy(A)
+
+
+def guess_op_set_stream(A, stream) -> None:
+    _check(_lib.guess_op_set_stream(A, stream))
+
+
+def guess_op_size(A) -> int:
+    return _lib.guess_op_size(A)
+
+
+def op_apply(A, x, y) -> None:
+    _check(_lib.op_apply(A, addr(x), addr(y)))
+
+
+def pcg_solve(A, b, x, rtol=1e-8, maxit=10000, stop_rule=STOP_RHS, check=True):
+    """Returns (status, iterations, relres)."""
+    it, rr = C.c_int(0), C.c_double(0.0)
+    code = _lib.pcg_solve_ex(A, addr(b), addr(x), rtol, maxit, stop_rule, C.byref(it), C.byref(rr))
+    if check and code not in (OK, ENOTCONV, EBREAKDOWN):
+        _check(code)
+    return code, it.value, rr.value
+
+
+# ---------------------------------------------------------------- contexts
+def guess_create(N, M, method, degree) -> int:
+    g = _lib.guess_create(N, M, method, degree)
+    if not g:
+        raise GuessError(EINVAL, _lib.guess_last_error().decode())
+    return g
+
+
+def guess_create_ex(N, M, method, degree=0, dtype=F64, eps_rel=0.0, op=None, stream=None) -> int:
+    o = guess_opts(N=N, M=M, method=method, degree=degree, dtype=dtype, eps_rel=eps_rel,
+                   op=op, stream=stream)
+    out = C.c_void_p()
+    _check(_lib.guess_create_ex(C.byref(o), C.byref(out)))
+    return out.value
+
+
+def guess_destroy(g) -> None:
+    _lib.guess_destroy(g)
+
+
+def guess_set_stream(g, stream) -> None:
+    _check(_lib.guess_set_stream(g, stream))
+
+
+def guess_set_op(g, A) -> None:
+    _check(_lib.guess_set_op(g, A))
+
+
+def guess_workspace_bytes(N, M, method, dtype) -> int:
+    return _lib.guess_workspace_bytes(N, M, method, dtype)
+
+
+def guess_form(g, b, x0) -> None:
+    _check(_lib.guess_form(g, addr(b), addr(x0)))
+
+
+def guess_update(g, x, Ax=None) -> None:
+    _check(_lib.guess_update(g, addr(x), addr(Ax)))
+
+
+def guess_get_info(g) -> dict:
+    info = guess_info()
+    _check(_lib.guess_get_info(g, C.byref(info)))
+    return info.as_dict()
+
+
+def guess_reset(g) -> None:
+    _check(_lib.guess_reset(g))
+
+
+def guess_extrap_weights(m, k):
+    buf = (C.c_double * k)()
+    _check(_lib.guess_extrap_weights(m, k, buf))
+    return list(buf)
+
+
+def guess_history_get(g, which, j, out) -> None:
+    _check(_lib.guess_history_get(g, which, j, addr(out)))
+
+
+def guess_profile(g, enable=True) -> None:
+    _check(_lib.guess_profile(g, 1 if enable else 0))
+
+
+def guess_kernel_times(g):
+    """Device ms of each kernel launched by the last form / update call."""
+    buf = (C.c_double * 8)()
+    n = C.c_int(0)
+    _check(_lib.guess_kernel_times(g, buf, 8, C.byref(n)))
+    return list(buf[: n.value])
+
+
+# ---------------------------------------------------------------- workload and vectors
+def workload_plane_wave_rhs(n, kvec, theta, amp, b, stream=None) -> None:
+    K = len(theta)
+    kv = (C.c_int * (3 * K))(*[int(v) for v in kvec])
+    th = (C.c_double * K)(*[float(v) for v in theta])
+    am = (C.c_double * K)(*[float(v) for v in amp])
+    _check(_lib.workload_plane_wave_rhs(n, K, kv, th, am, addr(b), stream))
+
+
+def vec_multidot(N, K, V, y, stream=None):
+    out = (C.c_double * K)()
+    _check(_lib.vec_multidot(N, K, addr(V), addr(y), out, stream))
+    return list(out)
+
+
+def vec_combine(N, K, V, c, y, stream=None) -> None:
+    cc = (C.c_double * K)(*[float(v) for v in c])
+    _check(_lib.vec_combine(N, K, addr(V), cc, addr(y), stream))
+
+
+def guess_copy_kernel(dst, src, nbytes, stream=None) -> None:
+    _check(_lib.guess_copy_kernel(addr(dst), addr(src), nbytes, stream))
+
+
+def guess_strerror(code) -> str:
+    return _lib.guess_strerror(code).decode()
+
+
+def guess_last_error() -> str:
+    return _lib.guess_last_error().decode()

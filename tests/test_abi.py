@@ -1,0 +1,107 @@
+"""Host-side checks of the libguess C ABI (no GPU needed).
+
+The library must load and export every function that include/libguess.h
+declares; host-only entry points (least-squares weights, argument
+validation, workspace sizes, error strings) are exercised directly.
+Compute entry points are only called by the GPU tests.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import extrap
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libguess.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2009_10863_amd import _build
+
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    from paper_2009_10863_amd import libguess
+
+    return libguess
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b([a-z_][a-z0-9_]*)\s*\([^;{]*\)\s*;", text)
+    return sorted(set(n for n in names if n not in ("if", "sizeof")))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("guess_create", "guess_form", "guess_update", "op_apply", "pcg_solve"):
+        assert n in names
+
+
+def test_library_exports_every_declared_function(L):
+    lib = ctypes.CDLL(L.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(L.EXPORTED)
+
+
+@pytest.mark.parametrize("k", range(1, 17))
+def test_host_weights_match_exact_rationals(L, k):
+    for m in range(0, k):
+        got = L.guess_extrap_weights(m, k)
+        ref = extrap.to_f64(extrap.beta_ls_exact(m, k))
+        assert max(abs(a - b) for a, b in zip(got, ref)) <= 1e-14 * max(1.0, float(extrap.lebesgue(extrap.beta_ls_exact(m, k))))
+
+
+def test_weight_argument_checks(L):
+    for m, k in [(-1, 4), (4, 4), (0, 0), (0, 17)]:
+        with pytest.raises(L.GuessError) as e:
+            L.guess_extrap_weights(m, k)
+        assert e.value.code == L.EINVAL
+
+
+def test_create_argument_checks(L):
+    bad = [
+        dict(N=0, M=4, method=L.EXTRAP, degree=1),
+        dict(N=10, M=0, method=L.EXTRAP, degree=0),
+        dict(N=10, M=17, method=L.PROJ),
+        dict(N=10, M=4, method=L.EXTRAP, degree=4),
+        dict(N=10, M=4, method=L.EXTRAP, degree=-1),
+        dict(N=10, M=4, method=7),
+        dict(N=10, M=4, method=L.EXTRAP, degree=1, dtype=9),
+    ]
+    for kw in bad:
+        with pytest.raises(L.GuessError) as e:
+            L.guess_create_ex(**kw)
+        assert e.value.code == L.EINVAL, kw
+    with pytest.raises(L.GuessError):
+        L.guess_create(10, 0, L.EXTRAP, 0)
+
+
+def test_operator_and_solver_argument_checks(L):
+    for args in [(0, 4, 4, 25.0, 10.0), (4, 4, 4, 0.0, 10.0), (4, 4, 4, 25.0, -1.0),
+                 (2048, 2048, 1024, 1.0, 1.0)]:
+        with pytest.raises(L.GuessError) as e:
+            L.guess_op_create(*args)
+        assert e.value.code == L.EINVAL
+    lib = L.lib()
+    it, rr = ctypes.c_int(), ctypes.c_double()
+    assert lib.pcg_solve(None, None, None, 1e-8, 10, ctypes.byref(it), ctypes.byref(rr)) == L.EINVAL
+    assert lib.op_apply(None, None, None) == L.EINVAL
+    assert lib.guess_form(None, None, None) == L.EINVAL
+    assert lib.guess_update(None, None, None) == L.EINVAL
+    assert "invalid" in L.guess_strerror(L.EINVAL)
+    assert L.guess_strerror(12345) == "unknown status"
+
+
+def test_workspace_bytes(L):
+    N, M = 256 ** 3, 8
+    col = N * 8
+    assert L.guess_workspace_bytes(N, M, L.EXTRAP, L.F64) == M * col
+    assert L.guess_workspace_bytes(N, M, L.EXTRAP, L.F16) == M * N * 2
+    assert L.guess_workspace_bytes(N, M, L.LAST, L.F64) == col
+    assert L.guess_workspace_bytes(N, M, L.PROJ, L.F64) >= 2 * M * col + N * 8
+    assert L.guess_workspace_bytes(N, M, L.PROJ, 9) == 0

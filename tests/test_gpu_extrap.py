@@ -1,0 +1,142 @@
+"""GPU parity of the extrapolation path (ring store + extrap_form) against the oracle.
+
+Tolerances: FP64 history -- guesses within relative 1e-12 of the oracle
+(inf-norm, relative to the oracle guess); stored FP64/FP32/FP16/BF16 values
+bit-exact (a deterministic rounding); FP32-accumulated guesses from
+reduced-precision history within the rigorous FP32 summation bound around
+the oracle's exact evaluation of the stored values.
+"""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import announce, dev, host, rel_inf
+from oracle import extrap, lowprec
+
+pytestmark = pytest.mark.gpu
+
+RAGGED_N = [1, 2, 3, 4, 5, 7, 1023, 1027, 32 ** 3, 33 ** 3 + 2]
+
+
+def _seq(lib, N, M, m, dtype, steps, seed):
+    import torch
+
+    L = lib
+    g = L.guess_create_ex(N, M, L.EXTRAP if M > 1 or m > 0 else L.LAST, m, L.DTYPES[dtype])
+    ref = extrap.ExtrapHistory(M, m, dtype)
+    X = synth.random_vectors(seed, steps, N) * np.linspace(0.5, 2.0, steps)[:, None]
+    x0 = torch.empty(N, dtype=torch.float64, device="cuda")
+    out = []
+    try:
+        for s in range(steps):
+            L.guess_form(g, None, x0)
+            out.append((host(x0), ref.form(N=N), list(ref.hist)))
+            xd = dev(X[s])
+            L.guess_update(g, xd)
+            ref.update(X[s])
+        info = L.guess_get_info(g)
+    finally:
+        L.guess_destroy(g)
+    return out, info
+
+
+@pytest.mark.parametrize("N", RAGGED_N)
+def test_f64_guesses_match_oracle(lib, N):
+    announce(f"extrap f64 N={N}")
+    M, m = 8, 2
+    res, info = _seq(lib, N, M, m, "f64", 12, seed=N)
+    assert info["count"] == M and info["head"] == 12 % M
+    for q, (got, want, _) in enumerate(res):
+        if q == 0:
+            assert not got.any()
+        else:
+            assert rel_inf(got, want) <= 1e-12, (N, q)
+
+
+@pytest.mark.parametrize("M,m", [(1, 0), (2, 1), (4, 2), (8, 1), (8, 3), (16, 3), (16, 4), (5, 4)])
+def test_f64_all_shapes(lib, M, m):
+    announce(f"extrap f64 M={M} m={m}")
+    res, _ = _seq(lib, 4099, M, m, "f64", M + 3, seed=100 + M + m)
+    for q, (got, want, _) in enumerate(res[1:], start=1):
+        assert rel_inf(got, want) <= 1e-12, (M, m, q)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16", "bf16"])
+def test_ring_store_bit_exact(lib, dtype):
+    """Stored values equal the oracle's two-step round-to-nearest-even."""
+    import torch
+
+    announce(f"ring store {dtype}")
+    L = lib
+    special = np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -11, 1 + 3 * 2 ** -11, 1 + 2 ** -24,
+                        1 + 3 * 2 ** -24, 65504.0, 65519.0, 2.0 ** -24, 3e-8, -0.0, 0.0, 1e-40,
+                        -2.5, 3.0e38, 1e300 if dtype == "f64" else 1.0])
+    for N in (1, 3, 5, 1030):
+        v = synth.random_vectors(N, 1, N)[0] * 10.0 ** np.random.default_rng(N).integers(-6, 4, N)
+        v[: min(N, len(special))] = special[: min(N, len(special))]
+        g = L.guess_create_ex(N, 2, L.EXTRAP, 0, L.DTYPES[dtype])
+        try:
+            L.guess_update(g, dev(v))
+            out = torch.empty(N, dtype=torch.float64, device="cuda")
+            L.guess_history_get(g, 0, 0, out)
+            got = host(out)
+        finally:
+            L.guess_destroy(g)
+        want = lowprec.round_store(v, dtype)
+        assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), (dtype, N)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("M,m", [(8, 2), (4, 1), (16, 3)])
+def test_lowprec_guess_within_fp32_bound(lib, dtype, M, m):
+    """|x0_gpu - sum beta_j h_j| <= (k+1) 2^-24 sum |beta_j h_j| + 2^-24 |x0| (h stored values)."""
+    announce(f"extrap {dtype} M={M} m={m}")
+    res, _ = _seq(lib, 5003, M, m, dtype, M + 2, seed=7)
+    u = 2.0 ** -24
+    for q, (got, want, hist) in enumerate(res[1:], start=1):
+        k = len(hist)
+        beta = extrap.to_f64(extrap.beta_ls_exact(min(m, k - 1), k))
+        mag = sum(abs(b) * np.abs(h) for b, h in zip(beta, hist))
+        bound = (k + 1) * u * mag + u * np.abs(want) + 1e-300
+        assert np.all(np.abs(got - want) <= bound), (dtype, q)
+
+
+def test_lowprec_error_vs_fp64_history(lib):
+    """Guess error against the unrounded FP64 history stays within Lambda u_s max|x|."""
+    announce("extrap low precision vs f64")
+    N, M, m = 2048, 8, 2
+    lam = float(extrap.lebesgue(extrap.beta_ls_exact(m, M)))
+    res64, _ = _seq(lib, N, M, m, "f64", M + 1, seed=3)
+    for dtype in ("f32", "f16", "bf16"):
+        res, _ = _seq(lib, N, M, m, dtype, M + 1, seed=3)
+        got, ref = res[-1][0], res64[-1][0]
+        X = synth.random_vectors(3, M + 1, N) * np.linspace(0.5, 2.0, M + 1)[:, None]
+        xmax = np.abs(X).max()
+        u = lowprec.UNIT_ROUNDOFF[dtype]
+        assert np.max(np.abs(got - ref)) <= (lam * u + (M + 1) * 2.0 ** -24 * lam) * xmax * 1.01, dtype
+
+
+def test_reset_and_zero_guess(lib):
+    import torch
+
+    announce("extrap reset / zero method")
+    L = lib
+    N = 100
+    g = L.guess_create(N, 4, L.EXTRAP, 1)
+    z = L.guess_create(N, 1, L.ZERO, 0)
+    x0 = torch.full((N,), 7.0, dtype=torch.float64, device="cuda")
+    try:
+        L.guess_update(g, dev(np.ones(N)))
+        L.guess_form(g, None, x0)
+        assert np.all(host(x0) == 1.0)
+        L.guess_reset(g)
+        assert L.guess_get_info(g)["count"] == 0
+        L.guess_form(g, None, x0)
+        assert not host(x0).any()
+        x0.fill_(3.0)
+        L.guess_form(z, None, x0)
+        L.guess_update(z, x0)
+        assert not host(x0).any()
+    finally:
+        L.guess_destroy(g)
+        L.guess_destroy(z)

@@ -1,0 +1,178 @@
+"""GPU parity of the operator (bit-exact) and Jacobi-PCG (iterations +-1) against the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from gpu_helpers import announce, dev, host, rel_inf
+from oracle import operator as op
+from oracle.pcg import pcg as oracle_pcg
+
+pytestmark = pytest.mark.gpu
+
+
+def make_op(L, n, kappa=None):
+    return L.guess_op_create(n, n, n, float((n + 1) ** 2), 10.0, None if kappa is None else dev(kappa))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 32, 33])
+def test_const_operator_bit_exact(lib, n):
+    import torch
+
+    announce(f"op const n={n}")
+    L = lib
+    A = make_op(L, n)
+    try:
+        x = synth.random_vectors(n, 1, n ** 3)[0]
+        y = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+        L.op_apply(A, dev(x), y)
+        got = host(y)
+    finally:
+        L.guess_op_destroy(A)
+    want = op.apply_const(x, n)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n", [1, 3, 17])
+def test_var_operator_bit_exact(lib, n):
+    import torch
+
+    announce(f"op var n={n}")
+    L = lib
+    kappa = np.exp(synth.gaussian_field(5, n, ell=0.2))
+    A = make_op(L, n, kappa)
+    try:
+        x = synth.random_vectors(n + 1, 1, n ** 3)[0]
+        y = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+        L.op_apply(A, dev(x), y)
+        got = host(y)
+    finally:
+        L.guess_op_destroy(A)
+    want = op.apply_var(x, n, op.face_coeffs(kappa, n))
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n,seed", [(16, 0), (32, 1), (31, 2)])
+def test_pcg_iterations_and_solution(lib, n, seed):
+    import torch
+
+    announce(f"pcg n={n}")
+    L = lib
+    params = synth.plane_wave_params(seed, 4)
+    b = synth.plane_wave_rhs(params, n, 0.25)
+    A = make_op(L, n)
+    try:
+        x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, it, rr = L.pcg_solve(A, dev(b), x, 1e-8, 5000)
+        xg = host(x)
+    finally:
+        L.guess_op_destroy(A)
+    Aop = op.Operator(n)
+    xo, ito, sto, rro = oracle_pcg(Aop, b, np.zeros_like(b), 1.0 / Aop.diag(), 1e-8, 5000)
+    assert st == L.OK and sto == 0
+    assert abs(it - ito) <= 1
+    assert rr <= 1e-8
+    true_res = np.linalg.norm(b - Aop(xg)) / np.linalg.norm(b)
+    assert true_res <= 1.5e-8
+    xe = op.dst_solve(b, n)
+    assert rel_inf(xg, xe) <= 1e-6
+    assert rel_inf(xg, xo) <= 1e-6
+
+
+def test_pcg_varcoef(lib):
+    import torch
+
+    announce("pcg var n=12")
+    L = lib
+    n = 12
+    kappa = np.exp(synth.gaussian_field(2, n, ell=0.1))
+    b = synth.random_vectors(4, 1, n ** 3)[0]
+    A = make_op(L, n, kappa)
+    try:
+        x = torch.zeros(n ** 3, dtype=torch.float64, device="cuda")
+        st, it, rr = L.pcg_solve(A, dev(b), x, 1e-8, 5000)
+        xg = host(x)
+    finally:
+        L.guess_op_destroy(A)
+    Aop = op.Operator(n, kappa_nodal=kappa)
+    xo, ito, sto, _ = oracle_pcg(Aop, b, np.zeros_like(b), 1.0 / Aop.diag(), 1e-8, 5000)
+    assert st == L.OK and abs(it - ito) <= 1
+    assert rel_inf(xg, xo) <= 1e-6
+
+
+def test_pcg_edge_cases(lib):
+    import torch
+
+    announce("pcg edge cases")
+    L = lib
+    n = 8
+    N = n ** 3
+    A = make_op(L, n)
+    try:
+        z = torch.zeros(N, dtype=torch.float64, device="cuda")
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        st, it, rr = L.pcg_solve(A, z, x, 1e-8, 100)           # zero right-hand side
+        assert st == L.OK and it == 0 and not host(x).any()
+        b = synth.random_vectors(1, 1, N)[0]
+        xe = op.dst_solve(b, n)
+        x = dev(xe)
+        st, it, rr = L.pcg_solve(A, dev(b), x, 1e-8, 100)       # exact guess
+        assert st == L.OK and it == 0
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        st, it, rr = L.pcg_solve(A, dev(b), x, 1e-14, 3)        # maxit
+        assert st == L.ENOTCONV and it == 3
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        st, it, rr = L.pcg_solve(A, dev(b), x, 1e-8, 0)         # no iterations allowed
+        assert st == L.ENOTCONV and it == 0
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        st, it, rr = L.pcg_solve(A, dev(1e-12 * b), x, 1e-8, 100, L.STOP_INITRESID)
+        assert st == L.OK and it == 0                           # paper's rule: absolute floor
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        st, it, _ = L.pcg_solve(A, dev(b), x, 1e-8, 1000, L.STOP_INITRESID)
+        Aop = op.Operator(n)
+        _, ito, _, _ = oracle_pcg(Aop, b, np.zeros_like(b), 1.0 / Aop.diag(), 1e-8, 1000, rule="initresid")
+        assert st == L.OK and abs(it - ito) <= 1
+    finally:
+        L.guess_op_destroy(A)
+
+
+def test_plane_wave_rhs_kernel(lib):
+    import torch
+
+    announce("workload rhs")
+    L = lib
+    params = synth.plane_wave_params(0, 16)
+    for n in (7, 32):
+        amp = synth.mode_amplitudes(params, 0.37)
+        b = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+        L.workload_plane_wave_rhs(n, params["k"].reshape(-1), params["theta"], amp, b)
+        want = synth.plane_wave_rhs(params, n, 0.37)
+        assert np.max(np.abs(host(b) - want)) <= 1e-12 * 16
+    n = 256
+    b = torch.empty(n ** 3, dtype=torch.float64, device="cuda")
+    amp = synth.mode_amplitudes(params, 1.0)
+    L.workload_plane_wave_rhs(n, params["k"].reshape(-1), params["theta"], amp, b)
+    idx = np.random.default_rng(0).integers(0, n ** 3, 4096)
+    idx = np.concatenate([idx, [0, n ** 3 - 1, n - 1, n * n - 1]])
+    want = synth.plane_wave_rhs_at(params, n, 1.0, idx)
+    assert np.max(np.abs(host(b)[idx] - want)) <= 1e-11 * 16
+
+
+def test_vector_kernels(lib):
+    import torch
+
+    announce("multidot / combine / copy")
+    L = lib
+    for N, K in [(1, 1), (1001, 3), (70000, 17)]:
+        V = synth.random_vectors(9, K, N)
+        y = synth.random_vectors(10, 1, N)[0]
+        got = L.vec_multidot(N, K, dev(V.reshape(-1)), dev(y))
+        want = V @ y
+        assert np.allclose(got, want, rtol=1e-12, atol=1e-12 * np.abs(V).sum(1).max())
+        c = np.linspace(-1, 1, K)
+        out = torch.empty(N, dtype=torch.float64, device="cuda")
+        L.vec_combine(N, K, dev(V.reshape(-1)), c, out)
+        assert rel_inf(host(out), c @ V) <= 1e-13
+    src = dev(np.arange(12345, dtype=np.float64))
+    dst = torch.zeros_like(src)
+    L.guess_copy_kernel(dst, src, 12345 * 8)
+    assert np.array_equal(host(dst), np.arange(12345, dtype=np.float64))
