@@ -11,6 +11,11 @@
 namespace lg {
 
 constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
+
+// Reduction kernels stream several vectors per step: allow up to 128 VGPRs
+// (4 waves per SIMD) so that every load of a step is in flight at once.
+#define LG_REDUCE_KERNEL \
+    __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxPartialBlocks = 2048;
 constexpr int kMaxDots = 2 * GUESS_MAX_M + 4;
@@ -39,7 +44,12 @@ template <int DT> __device__ __forceinline__ typename Elem<DT>::T to_store(doubl
 template <> __device__ __forceinline__ double to_store<GUESS_F64>(double v) { return v; }
 template <> __device__ __forceinline__ float to_store<GUESS_F32>(double v) { return (float)v; }
 template <> __device__ __forceinline__ _Float16 to_store<GUESS_F16>(double v) {
-    return (_Float16)(float)v;
+    // The FP32 value is made opaque so that the compiler cannot merge the two
+    // conversions into one direct FP64 -> FP16 rounding (which differs from
+    // the two-step rounding when the FP32 value lands on an FP16 midpoint).
+    float f = (float)v;
+    asm volatile("" : "+v"(f));
+    return (_Float16)f;
 }
 template <> __device__ __forceinline__ uint16_t to_store<GUESS_BF16>(double v) {
     return f32_to_bf16_bits((float)v);
@@ -57,76 +67,92 @@ template <int DT> __device__ __forceinline__ double to_f64(typename Elem<DT>::T 
 }
 template <> __device__ __forceinline__ double to_f64<GUESS_F64>(double v) { return v; }
 
-// ------------------------------------------------------------------ 4-wide access
-// Every streaming kernel moves 4 consecutive elements per thread and step:
-// 32 B of FP64, 16 B of FP32, 8 B of FP16/BF16.  Pointers are 16-B aligned.
+// ------------------------------------------------------------------ work split
+// Vectors are processed in tiles of 256 consecutive elements, one tile per
+// wave and step.  Lane L of the wave owns the element pairs (2L, 2L+1) and
+// (128+2L, 129+2L) of the tile -- its "chunk" -- so that every load or store
+// instruction of the wave covers one contiguous range (1 KiB for FP64).
+// Elements past the last full tile (N mod 256 of them) form the ragged tail
+// and are handled one per thread by workgroup 0.
+__host__ __device__ __forceinline__ int64_t nchunks(int64_t N) { return (N >> 8) << 6; }
+__host__ __device__ __forceinline__ int64_t tail_start(int64_t N) { return (N >> 8) << 8; }
+__host__ __device__ __forceinline__ int tail_count(int64_t N) { return (int)(N & 255); }
+// first element of chunk c's first pair; the second pair starts 128 later
+__device__ __forceinline__ int64_t chunk_elem(int64_t c) { return ((c >> 6) << 8) + ((c & 63) << 1); }
+
 typedef double d2 __attribute__((ext_vector_type(2)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 
+// The 4 values of a chunk, in the order (2L, 2L+1, 128+2L, 129+2L).
 struct V4 { double v[4]; };
-
-template <int DT> __device__ __forceinline__ V4 load4(const void *p, int64_t c);
-template <> __device__ __forceinline__ V4 load4<GUESS_F64>(const void *p, int64_t c) {
-    const d2 *q = reinterpret_cast<const d2 *>(p) + 2 * c;
-    d2 a = __builtin_nontemporal_load(q), b = __builtin_nontemporal_load(q + 1);
-    return V4{{a.x, a.y, b.x, b.y}};
-}
-template <> __device__ __forceinline__ V4 load4<GUESS_F32>(const void *p, int64_t c) {
-    f4 a = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p) + c);
-    return V4{{(double)a.x, (double)a.y, (double)a.z, (double)a.w}};
-}
-template <> __device__ __forceinline__ V4 load4<GUESS_F16>(const void *p, int64_t c) {
-    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-    h4 a = __builtin_nontemporal_load(reinterpret_cast<const h4 *>(p) + c);
-    return V4{{(double)(float)a.x, (double)(float)a.y, (double)(float)a.z, (double)(float)a.w}};
-}
-template <> __device__ __forceinline__ V4 load4<GUESS_BF16>(const void *p, int64_t c) {
-    u2 a = __builtin_nontemporal_load(reinterpret_cast<const u2 *>(p) + c);
-    return V4{{(double)__uint_as_float(a.x << 16), (double)__uint_as_float(a.x & 0xffff0000u),
-               (double)__uint_as_float(a.y << 16), (double)__uint_as_float(a.y & 0xffff0000u)}};
-}
-
-// FP32 view of 4 stored elements (for FP32-accumulating kernels).
 struct F4 { float v[4]; };
-template <int DT> __device__ __forceinline__ F4 load4f(const void *p, int64_t c);
-template <> __device__ __forceinline__ F4 load4f<GUESS_F32>(const void *p, int64_t c) {
-    f4 a = __builtin_nontemporal_load(reinterpret_cast<const f4 *>(p) + c);
-    return F4{{a.x, a.y, a.z, a.w}};
+
+template <int DT> struct Pair;
+template <> struct Pair<GUESS_F64> { using T = d2; };
+template <> struct Pair<GUESS_F32> { using T = f2; };
+template <> struct Pair<GUESS_F16> { using T = h2; };
+template <> struct Pair<GUESS_BF16> { using T = uint32_t; };
+
+template <int DT>
+__device__ __forceinline__ typename Pair<DT>::T ldpair(const void *p, int64_t e) {
+    using T = typename Pair<DT>::T;
+    return __builtin_nontemporal_load(reinterpret_cast<const T *>(p) + (e >> 1));
 }
-template <> __device__ __forceinline__ F4 load4f<GUESS_F16>(const void *p, int64_t c) {
-    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-    h4 a = __builtin_nontemporal_load(reinterpret_cast<const h4 *>(p) + c);
-    return F4{{(float)a.x, (float)a.y, (float)a.z, (float)a.w}};
-}
-template <> __device__ __forceinline__ F4 load4f<GUESS_BF16>(const void *p, int64_t c) {
-    u2 a = __builtin_nontemporal_load(reinterpret_cast<const u2 *>(p) + c);
-    return F4{{__uint_as_float(a.x << 16), __uint_as_float(a.x & 0xffff0000u),
-               __uint_as_float(a.y << 16), __uint_as_float(a.y & 0xffff0000u)}};
+template <int DT>
+__device__ __forceinline__ void stpair(void *p, int64_t e, typename Pair<DT>::T v) {
+    using T = typename Pair<DT>::T;
+    __builtin_nontemporal_store(v, reinterpret_cast<T *>(p) + (e >> 1));
 }
 
-template <int DT> __device__ __forceinline__ void store4(void *p, int64_t c, const V4 &x);
-template <> __device__ __forceinline__ void store4<GUESS_F64>(void *p, int64_t c, const V4 &x) {
-    d2 *q = reinterpret_cast<d2 *>(p) + 2 * c;
-    d2 a = {x.v[0], x.v[1]}, b = {x.v[2], x.v[3]};
-    __builtin_nontemporal_store(a, q);
-    __builtin_nontemporal_store(b, q + 1);
+template <int DT> __device__ __forceinline__ void widen2(typename Pair<DT>::T v, float &a, float &b);
+template <> __device__ __forceinline__ void widen2<GUESS_F32>(f2 v, float &a, float &b) { a = v.x; b = v.y; }
+template <> __device__ __forceinline__ void widen2<GUESS_F16>(h2 v, float &a, float &b) {
+    a = (float)v.x;
+    b = (float)v.y;
 }
-template <> __device__ __forceinline__ void store4<GUESS_F32>(void *p, int64_t c, const V4 &x) {
-    f4 a = {(float)x.v[0], (float)x.v[1], (float)x.v[2], (float)x.v[3]};
-    __builtin_nontemporal_store(a, reinterpret_cast<f4 *>(p) + c);
+template <> __device__ __forceinline__ void widen2<GUESS_BF16>(uint32_t v, float &a, float &b) {
+    a = __uint_as_float(v << 16);
+    b = __uint_as_float(v & 0xffff0000u);
 }
-template <> __device__ __forceinline__ void store4<GUESS_F16>(void *p, int64_t c, const V4 &x) {
-    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-    h4 a = {to_store<GUESS_F16>(x.v[0]), to_store<GUESS_F16>(x.v[1]),
-            to_store<GUESS_F16>(x.v[2]), to_store<GUESS_F16>(x.v[3])};
-    __builtin_nontemporal_store(a, reinterpret_cast<h4 *>(p) + c);
+
+template <int DT>
+__device__ __forceinline__ V4 load4(const void *p, int64_t c) {
+    const int64_t e = chunk_elem(c);
+    if constexpr (DT == GUESS_F64) {
+        const d2 a = ldpair<DT>(p, e), b = ldpair<DT>(p, e + 128);
+        return V4{{a.x, a.y, b.x, b.y}};
+    } else {
+        float a0, a1, b0, b1;
+        widen2<DT>(ldpair<DT>(p, e), a0, a1);
+        widen2<DT>(ldpair<DT>(p, e + 128), b0, b1);
+        return V4{{(double)a0, (double)a1, (double)b0, (double)b1}};
+    }
 }
-template <> __device__ __forceinline__ void store4<GUESS_BF16>(void *p, int64_t c, const V4 &x) {
-    u2 a;
-    a.x = (uint32_t)to_store<GUESS_BF16>(x.v[0]) | ((uint32_t)to_store<GUESS_BF16>(x.v[1]) << 16);
-    a.y = (uint32_t)to_store<GUESS_BF16>(x.v[2]) | ((uint32_t)to_store<GUESS_BF16>(x.v[3]) << 16);
-    __builtin_nontemporal_store(a, reinterpret_cast<u2 *>(p) + c);
+
+// FP32 view of a chunk of reduced-precision storage (FP32-accumulating kernels).
+template <int DT>
+__device__ __forceinline__ F4 load4f(const void *p, int64_t c) {
+    const int64_t e = chunk_elem(c);
+    F4 r;
+    widen2<DT>(ldpair<DT>(p, e), r.v[0], r.v[1]);
+    widen2<DT>(ldpair<DT>(p, e + 128), r.v[2], r.v[3]);
+    return r;
+}
+
+template <int DT>
+__device__ __forceinline__ typename Pair<DT>::T narrow2(double a, double b) {
+    if constexpr (DT == GUESS_F64) return d2{a, b};
+    else if constexpr (DT == GUESS_F32) return f2{(float)a, (float)b};
+    else if constexpr (DT == GUESS_F16) return h2{to_store<GUESS_F16>(a), to_store<GUESS_F16>(b)};
+    else return (uint32_t)to_store<GUESS_BF16>(a) | ((uint32_t)to_store<GUESS_BF16>(b) << 16);
+}
+
+template <int DT>
+__device__ __forceinline__ void store4(void *p, int64_t c, const V4 &x) {
+    const int64_t e = chunk_elem(c);
+    stpair<DT>(p, e, narrow2<DT>(x.v[0], x.v[1]));
+    stpair<DT>(p, e + 128, narrow2<DT>(x.v[2], x.v[3]));
 }
 
 // Scalar element access (ragged tails).
@@ -173,26 +199,10 @@ __device__ __forceinline__ void block_partials(const double (&v)[ND], double *pa
     __syncthreads();
 }
 
-// True in exactly one workgroup: the last to arrive.  All partial results
-// written before the call by every workgroup are visible to it afterwards.
-// The last workgroup re-arms the ticket for the next launch.
-__device__ __forceinline__ bool last_block(unsigned int *ticket) {
-    __shared__ int is_last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int t = atomicAdd(ticket, 1u);
-        is_last = (t == gridDim.x - 1);
-        if (is_last) atomicExch(ticket, 0u);
-    }
-    __syncthreads();
-    if (is_last) __threadfence();
-    return is_last != 0;
-}
-
-// In the last workgroup: total of value j over all nb partial rows, summed in
-// a fixed order (thread t takes rows t, t+256, ...; then a fixed tree).
-// Every thread of the workgroup receives all ND totals.
+// Total of value j over nb partial rows (written by an earlier kernel),
+// summed in a fixed order (thread t takes rows t, t+256, ...; then a fixed
+// tree), so every workgroup that calls it obtains identical totals.  Every
+// thread of the workgroup receives all ND totals.
 template <int ND>
 __device__ __forceinline__ void final_sums(const double *part, int nb, double (&tot)[ND],
                                            double *lds) {

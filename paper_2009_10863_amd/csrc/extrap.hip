@@ -20,7 +20,7 @@ struct ExtrapArgs {
 template <int DT, int K>
 __global__ __launch_bounds__(kBlock) void extrap_form_kernel(ExtrapArgs a, double *__restrict__ x0,
                                                              int64_t N) {
-    const int64_t nc = N >> 2;
+    const int64_t nc = nchunks(N);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
         if constexpr (DT == GUESS_F64) {
@@ -54,9 +54,9 @@ __global__ __launch_bounds__(kBlock) void extrap_form_kernel(ExtrapArgs a, doubl
         }
     }
     // ragged tail (N mod 4 unknowns), same arithmetic
-    const int rem = (int)(N & 3);
+    const int rem = tail_count(N);
     if (blockIdx.x == 0 && threadIdx.x < rem) {
-        const int64_t i = (nc << 2) + threadIdx.x;
+        const int64_t i = tail_start(N) + threadIdx.x;
         if constexpr (DT == GUESS_F64) {
             double acc = a.beta[0] * load1<DT>(a.slot[0], i);
             for (int j = 1; j < K; ++j) acc = __builtin_fma(a.beta[j], load1<DT>(a.slot[j], i), acc);
@@ -73,25 +73,25 @@ __global__ __launch_bounds__(kBlock) void extrap_form_kernel(ExtrapArgs a, doubl
 template <int DT>
 __global__ __launch_bounds__(kBlock) void ring_store_kernel(const double *__restrict__ x,
                                                             void *__restrict__ slot, int64_t N) {
-    const int64_t nc = N >> 2;
+    const int64_t nc = nchunks(N);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride)
         store4<DT>(slot, c, load4<GUESS_F64>(x, c));
-    const int rem = (int)(N & 3);
+    const int rem = tail_count(N);
     if (blockIdx.x == 0 && threadIdx.x < rem) {
-        const int64_t i = (nc << 2) + threadIdx.x;
+        const int64_t i = tail_start(N) + threadIdx.x;
         store1<DT>(slot, i, x[i]);
     }
 }
 
 __global__ __launch_bounds__(kBlock) void fill_zero_kernel(double *__restrict__ x, int64_t N) {
-    const int64_t nc = N >> 2;
+    const int64_t nc = nchunks(N);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const V4 z{{0.0, 0.0, 0.0, 0.0}};
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride)
         store4<GUESS_F64>(x, c, z);
-    const int rem = (int)(N & 3);
-    if (blockIdx.x == 0 && threadIdx.x < rem) x[(nc << 2) + threadIdx.x] = 0.0;
+    const int rem = tail_count(N);
+    if (blockIdx.x == 0 && threadIdx.x < rem) x[tail_start(N) + threadIdx.x] = 0.0;
 }
 
 template <int DT>
@@ -139,7 +139,7 @@ int launch_extrap_form(int dtype, int k, const void *const *slots, const double 
         a.slot[j] = slots[j];
         a.beta[j] = beta[j];
     }
-    const int grid = stream_grid(N >> 2, grid_cap());
+    const int grid = stream_grid(nchunks(N), grid_cap());
     int rc = GUESS_EINVAL;
     kev(ev, 0, s);
     switch (dtype) {
@@ -154,7 +154,7 @@ int launch_extrap_form(int dtype, int k, const void *const *slots, const double 
 }
 
 int launch_ring_store(int dtype, const double *x, void *slot, int64_t N, hipStream_t s, KEvents *ev) {
-    const int grid = stream_grid(N >> 2, grid_cap());
+    const int grid = stream_grid(nchunks(N), grid_cap());
     kev(ev, 0, s);
     if (ev) ev->count = 1;
     switch (dtype) {
@@ -169,7 +169,7 @@ int launch_ring_store(int dtype, const double *x, void *slot, int64_t N, hipStre
 }
 
 int launch_fill_zero(double *x, int64_t N, hipStream_t s) {
-    fill_zero_kernel<<<stream_grid(N >> 2, grid_cap()), kBlock, 0, s>>>(x, N);
+    fill_zero_kernel<<<stream_grid(nchunks(N), grid_cap()), kBlock, 0, s>>>(x, N);
     return GUESS_OK;
 }
 

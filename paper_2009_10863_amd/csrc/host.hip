@@ -99,7 +99,8 @@ struct guess_op {
     lg::Grid g{};
     hipStream_t stream = nullptr;
     double *kx = nullptr, *ky = nullptr, *kz = nullptr, *dinv = nullptr;
-    double *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;
+    double *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
+    double *part_a = nullptr, *part_b = nullptr;  // per-workgroup partial sums of the two PCG kernels
     lg::PcgState *st = nullptr;
     lg::PcgState *host_st = nullptr;  // pinned
 };
@@ -107,7 +108,8 @@ struct guess_op {
 static void op_free(guess_op *A) {
     if (!A) return;
     for (void *ptr : {(void *)A->kx, (void *)A->ky, (void *)A->kz, (void *)A->dinv, (void *)A->r,
-                      (void *)A->p, (void *)A->q, (void *)A->part, (void *)A->st})
+                      (void *)A->p[0], (void *)A->p[1], (void *)A->q, (void *)A->part_a, (void *)A->part_b,
+                      (void *)A->st})
         if (ptr) (void)hipFree(ptr);
     if (A->host_st) (void)hipHostFree(A->host_st);
     delete A;
@@ -132,6 +134,9 @@ extern "C" int guess_op_create(int nx, int ny, int nz, double inv_h2, double shi
     A->g.c = inv_h2;
     A->g.shift = shift;
     A->g.dinv_const = 1.0 / (inv_h2 * 6.0 + shift);
+    A->g.fnx = lg::make_fastdiv((uint32_t)nx);
+    A->g.fny = lg::make_fastdiv((uint32_t)ny);
+    A->g.aligned = (nx % 2) == 0;
     auto alloc = [&](void **ptr, size_t bytes) -> int {
         hipError_t e = hipMalloc(ptr, bytes);
         if (e != hipSuccess) {
@@ -142,9 +147,11 @@ extern "C" int guess_op_create(int nx, int ny, int nz, double inv_h2, double shi
     };
     int rc = GUESS_OK;
     if (rc == GUESS_OK) rc = alloc((void **)&A->r, n * 8);
-    if (rc == GUESS_OK) rc = alloc((void **)&A->p, n * 8);
+    if (rc == GUESS_OK) rc = alloc((void **)&A->p[0], n * 8);
+    if (rc == GUESS_OK) rc = alloc((void **)&A->p[1], n * 8);
     if (rc == GUESS_OK) rc = alloc((void **)&A->q, n * 8);
-    if (rc == GUESS_OK) rc = alloc((void **)&A->part, sizeof(double) * lg::kMaxPartialBlocks * lg::kMaxDots);
+    if (rc == GUESS_OK) rc = alloc((void **)&A->part_a, sizeof(double) * lg::kMaxPartialBlocks);
+    if (rc == GUESS_OK) rc = alloc((void **)&A->part_b, sizeof(double) * lg::kMaxPartialBlocks * 3);
     if (rc == GUESS_OK) rc = alloc((void **)&A->st, sizeof(lg::PcgState));
     if (rc == GUESS_OK && hipHostMalloc((void **)&A->host_st, sizeof(lg::PcgState), hipHostMallocDefault) != hipSuccess)
         rc = fail(GUESS_ENOMEM, "guess_op_create: pinned allocation failed");
@@ -188,6 +195,7 @@ extern "C" int64_t guess_op_size(guess_op_t A) { return A ? A->g.n : 0; }
 extern "C" int op_apply(guess_op_t A, const double *x, double *y) {
     if (!A || !x || !y) return fail(GUESS_EINVAL, "op_apply: NULL argument");
     if (x == y) return fail(GUESS_EINVAL, "op_apply: x and y must not alias");
+    if (!aligned16(x) || !aligned16(y)) return fail(GUESS_EINVAL, "op_apply: vectors must be 16-byte aligned");
     lg::launch_op_apply(A->g, x, y, A->stream);
     return check_launch("op_apply");
 }
@@ -198,6 +206,7 @@ extern "C" int pcg_solve_ex(guess_op_t A, const double *b, double *x, double rto
     if (relres) *relres = 0.0;
     if (!A || !b || !x) return fail(GUESS_EINVAL, "pcg_solve: NULL argument");
     if (b == x) return fail(GUESS_EINVAL, "pcg_solve: b and x must not alias");
+    if (!aligned16(b) || !aligned16(x)) return fail(GUESS_EINVAL, "pcg_solve: vectors must be 16-byte aligned");
     if (!(rtol >= 0.0) || maxit < 0) return fail(GUESS_EINVAL, "pcg_solve: need rtol >= 0 and maxit >= 0");
     if (stop_rule != GUESS_STOP_RHS && stop_rule != GUESS_STOP_INITRESID)
         return fail(GUESS_EINVAL, "pcg_solve: unknown stopping rule");
@@ -206,28 +215,36 @@ extern "C" int pcg_solve_ex(guess_op_t A, const double *b, double *x, double rto
     init.rule = stop_rule;
     *A->host_st = init;
     LG_HIP(hipMemcpyAsync(A->st, A->host_st, sizeof init, hipMemcpyHostToDevice, s));
-    lg::launch_pcg_init(A->g, b, x, A->r, A->p, A->part, A->st, rtol, stop_rule, s);
+    lg::launch_pcg_init(A->g, b, x, A->r, A->part_b, s);
     LG_TRY(check_launch("pcg_init"));
     auto read_state = [&]() -> int {
         LG_HIP(hipMemcpyAsync(A->host_st, A->st, sizeof(lg::PcgState), hipMemcpyDeviceToHost, s));
         LG_HIP(hipStreamSynchronize(s));
         return GUESS_OK;
     };
-    LG_TRY(read_state());
-    int launched = 0;
-    // Iterations are enqueued in batches; kernels of a batch return at once
-    // after convergence, so the count stays exact.  Batches grow with the
+    // Iteration k's first kernel also runs the stop test on r_{k-1}, so the
+    // test after the last allowed iteration is a separate check.  Iterations
+    // are enqueued in batches; kernels of a batch return at once after
+    // convergence, so the count stays exact.  Batches grow with the
     // iteration count so that short solves do not pay for long batches.
-    while (!(A->host_st->converged | A->host_st->breakdown) && launched < maxit) {
-        int chunk = launched < 4 ? 2 : (launched < 32 ? 4 : (launched < 128 ? 8 : 16));
-        if (chunk > maxit - launched) chunk = maxit - launched;
-        for (int c = 0; c < chunk; ++c) lg::launch_pcg_iter(A->g, x, A->r, A->p, A->q, A->part, A->st, s);
+    int k = 1;
+    while (k <= maxit) {
+        int chunk = k <= 4 ? 2 : (k <= 32 ? 4 : (k <= 128 ? 8 : 16));
+        if (chunk > maxit - k + 1) chunk = maxit - k + 1;
+        for (int c = 0; c < chunk; ++c, ++k)
+            lg::launch_pcg_iter(A->g, x, A->r, A->p, A->q, A->part_a, A->part_b, A->st, k, rtol, s);
         LG_TRY(check_launch("pcg_iter"));
-        launched += chunk;
+        LG_TRY(read_state());
+        if (A->host_st->converged | A->host_st->breakdown) break;
+    }
+    if (!(A->host_st->converged | A->host_st->breakdown)) {
+        lg::launch_pcg_check(A->g, A->part_b, A->st, k, rtol, s);
+        LG_TRY(check_launch("pcg_check"));
         LG_TRY(read_state());
     }
     const lg::PcgState &st = *A->host_st;
-    if (iters) *iters = st.it;
+    const int its = (st.converged | st.breakdown) ? st.it : maxit;
+    if (iters) *iters = its;
     if (relres) *relres = st.bb > 0.0 ? std::sqrt(st.rr) / std::sqrt(st.bb) : std::sqrt(st.rr);
     if (st.converged) return GUESS_OK;
     if (st.breakdown) return fail(GUESS_EBREAKDOWN, "pcg_solve: breakdown (p^T A p <= 0 or not finite)");
@@ -716,7 +733,7 @@ extern "C" int vec_multidot(int64_t N, int K, const double *V, const double *y, 
             return fail(GUESS_ENOMEM, "vec_multidot: allocation failed");
         }
     }
-    LG_TRY(lg::launch_multidot(N, K, V, y, g_vec.part, nullptr, g_vec.out, s));
+    LG_TRY(lg::launch_multidot(N, K, V, y, g_vec.part, g_vec.out, s));
     LG_TRY(check_launch("vec_multidot"));
     LG_HIP(hipMemcpyAsync(out, g_vec.out, sizeof(double) * K, hipMemcpyDeviceToHost, s));
     LG_HIP(hipStreamSynchronize(s));

@@ -33,7 +33,6 @@ struct ProjState {
     int form_d;             // columns used by the last guess (written by proj_combine)
     int upd_d;              // columns at the start of the last update (written by proj_apply)
     int pad;
-    unsigned int ticket[4]; // last-workgroup counters of the reduction kernels
     double eps_rel;
     double nu0sq, nusq, nu0, nu;
     double scale[GUESS_MAX_M];   // column j of X (and B) = scale[j] * stored column j
@@ -42,11 +41,11 @@ struct ProjState {
     double cs[GUESS_MAX_M];      // update: c[j] * scale[j]
 };
 
-// Device-resident state of a PCG solve.
+// Device-resident state of a PCG solve (rho of iteration k in rho[k & 1]).
 struct PcgState {
-    double rho, alpha, beta, rr, bb, rr0, thresh;
+    double rho[2];
+    double alpha, rr, bb, rr0, thresh;
     int it, converged, breakdown, rule;
-    unsigned int ticket[4];
 };
 
 // ---- extrapolation (extrap.hip)
@@ -76,15 +75,16 @@ int launch_proj_update(const ProjBufs &p, const Grid *g, const double *x, const 
 int launch_build_faces(Grid &g, const double *kappa, double *kx, double *ky, double *kz,
                        double *dinv, hipStream_t s);
 int launch_op_apply(const Grid &g, const double *x, double *y, hipStream_t s);
-int launch_pcg_init(const Grid &g, const double *b, const double *x, double *r, double *p,
-                    double *part, PcgState *st, double rtol, int rule, hipStream_t s);
-int launch_pcg_iter(const Grid &g, double *x, double *r, double *p, double *q, double *part,
-                    PcgState *st, hipStream_t s);
+int launch_pcg_init(const Grid &g, const double *b, const double *x, double *r, double *part_b,
+                    hipStream_t s);
+int launch_pcg_iter(const Grid &g, double *x, double *r, double *const p[2], double *q, double *part_a,
+                    double *part_b, PcgState *st, int k, double rtol, hipStream_t s);
+int launch_pcg_check(const Grid &g, const double *part_b, PcgState *st, int k, double rtol, hipStream_t s);
 int pcg_grid(const Grid &g);
 
 // ---- vectors and workload (vec.hip)
 int launch_multidot(int64_t N, int K, const double *V, const double *y, double *part,
-                    unsigned int *ticket, double *out_dev, hipStream_t s);
+                    double *out_dev, hipStream_t s);
 int launch_combine(int64_t N, int K, const double *V, const double *c, double *y, hipStream_t s);
 int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 int launch_plane_wave_rhs(int n, int K, const double *tabx, const double *taby,

@@ -40,9 +40,8 @@ __global__ __launch_bounds__(kBlock) void multidot_final_kernel(int nb, int K0, 
     if (threadIdx.x < KN) out[K0 + threadIdx.x] = tot[threadIdx.x];
 }
 
-int launch_multidot(int64_t N, int K, const double *V, const double *y, double *part, unsigned int *ticket,
-                    double *out_dev, hipStream_t s) {
-    (void)ticket;
+int launch_multidot(int64_t N, int K, const double *V, const double *y, double *part, double *out_dev,
+                    hipStream_t s) {
     if (K < 1 || K > kMaxVecK) return GUESS_EINVAL;
     const int gr = stream_grid(N, reduce_blocks());
     for (int k0 = 0; k0 < K; k0 += 8) {

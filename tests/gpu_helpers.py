@@ -25,3 +25,15 @@ def rel_inf(a, b):
     a, b = np.asarray(a), np.asarray(b)
     scale = max(float(np.max(np.abs(b))) if b.size else 0.0, 1e-300)
     return float(np.max(np.abs(a - b))) / scale if a.size else 0.0
+
+
+def assert_within(got, want, bound, hist=None, label=""):
+    """Elementwise |got - want| <= bound; on failure report the worst elements."""
+    got, want, bound = np.asarray(got), np.asarray(want), np.asarray(bound)
+    bad = np.nonzero(~(np.abs(got - want) <= bound))[0]
+    if bad.size:
+        lines = [f"{label}: {bad.size} elements outside the bound"]
+        for i in bad[:5]:
+            h = "" if hist is None else " hist=" + repr([float(v[i]) for v in hist])
+            lines.append(f"  i={i} got={got[i]!r} want={want[i]!r} bound={bound[i]!r}{h}")
+        raise AssertionError("\n".join(lines))

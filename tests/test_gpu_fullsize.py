@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from gpu_helpers import announce, dev, host, rel_inf
+from gpu_helpers import announce, assert_within, dev, host, rel_inf
 from oracle import extrap, lowprec
 from oracle import operator as op
 from oracle.projection import AOrthoProjection
@@ -53,7 +53,7 @@ def test_extrap_256_sampled(lib, dtype):
         assert rel_inf(got, want) <= 1e-12
     else:
         mag = sum(abs(b) * np.abs(h) for b, h in zip(beta, hist))
-        assert np.all(np.abs(got - want) <= (M + 1) * 2.0 ** -24 * mag + 2.0 ** -24 * np.abs(want))
+        assert_within(got, want, (M + 1) * 2.0 ** -24 * mag + 2.0 ** -24 * np.abs(want), hist, dtype)
 
 
 def test_proj_256_full(lib):
