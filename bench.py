@@ -73,7 +73,64 @@ def parse():
     p.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     p.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
     p.add_argument("--cpu-steps", type=int, default=2)
+    p.add_argument("--precision-steps", type=int, default=10,
+                   help="timed steps of each FP32/FP16/BF16 history run (0: skip)")
+    p.add_argument("--calibrate-copy", action="store_true",
+                   help="only run the plain copy kernel (1 GiB -> 1 GiB, 5 launches); used to scale "
+                        "the FETCH_SIZE / WRITE_SIZE counters of a profiled run")
     return p.parse_args()
+
+
+def copy_roof(L, nbytes=1 << 30, reps=5):
+    """Bandwidth of the library's plain copy kernel (nbytes read + nbytes written)."""
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    L.guess_copy_kernel(dst, src, nbytes, L.stream_handle())
+    ts = []
+    for _ in range(reps):
+        ev[0].record()
+        L.guess_copy_kernel(dst, src, nbytes, L.stream_handle())
+        ev[1].record()
+        torch.cuda.synchronize()
+        ts.append(ev[0].elapsed_time(ev[1]))
+    del src, dst
+    t = sorted(ts)[len(ts) // 2]
+    return 2 * nbytes / (t * 1e-3) / 1e9
+
+
+def hbm_traffic(kernel):
+    """Counter-measured HBM bytes per launch of `kernel`, if still valid.
+
+    Read from profiles/hbm_traffic.txt (written from two rocprofv3 --pmc runs,
+    FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration); the
+    entry is ignored (None) when the kernel sources changed since then.
+    """
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        line = line.strip()
+        if line and not line.startswith("#") and "=" in line:
+            k, v = line.split("=", 1)
+            rec[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in sorted(rec.get("sources", "").split(",")):
+        if not f:
+            continue
+        fp = os.path.join(ROOT, f)
+        if not os.path.exists(fp):
+            return None
+        h.update(open(fp, "rb").read())
+    if rec.get("sha256") != h.hexdigest():
+        return None
+    v = rec.get(f"{kernel}.bytes_per_launch")
+    return float(v) if v else None
 
 
 def cpu_baseline(args, s_bytes):
@@ -145,73 +202,103 @@ def main():
     from paper_2009_10863_amd.sequence import Operator, PlaneWaveRHS
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        gbps = copy_roof(L, 1 << 30, 5)
+        print(json.dumps({"copy_kernel_GBps": gbps, "bytes_read_per_launch": 1 << 30,
+                          "bytes_written_per_launch": 1 << 30}), flush=True)
+        return
+    roof = copy_roof(L)
     n, N, M = args.n, args.n ** 3, args.M
-    s = L.ELEM_BYTES[L.DTYPES[args.dtype]]
     methods = [m.strip() for m in args.methods.split(",") if m.strip()]
     op = Operator(n, 10.0)
     params = synth.plane_wave_params(args.seed, args.modes)
     rhs = PlaneWaveRHS(params, n)
     b = torch.empty(N, dtype=torch.float64, device="cuda")
-    ctx, xs = {}, {}
-    for m in methods:
-        ctx[m] = L.guess_create_ex(N, 1 if m == "last" else M, L.METHODS[m], args.degree if m == "extrap" else 0,
-                                   L.DTYPES[args.dtype], 1e-6, op.handle, L.stream_handle())
-        L.guess_profile(ctx[m], True)
-        xs[m] = torch.zeros(N, dtype=torch.float64, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    stats = {m: {"iters": [], "guess_ms": 0.0, "guess_bytes": 0.0, "solve_ms": 0.0, "relres": []} for m in methods}
-    kstat = {}    # kernel -> [launches, ms, bytes]
 
-    def one_step(step, timed):
-        t = step * args.dt
-        rhs(t, b)
+    def run(dtype, steps, warmup, shadow=False):
+        """Time `steps` steps after `warmup` untimed ones; with `shadow`, an FP64
+        context per method is fed the same solutions, and the guess error of the
+        reduced-precision history against it is recorded."""
+        s = L.ELEM_BYTES[L.DTYPES[dtype]]
+        ctx, xs, sh, x64 = {}, {}, {}, None
         for m in methods:
-            g, x = ctx[m], xs[m]
-            inf0 = L.guess_get_info(g)
-            kd = inf0["count"]
-            kd_form = min(kd, M) if m != "proj" else kd
-            L.guess_form(g, b, x)
-            tf = L.guess_kernel_times(g)
-            ev[0].record()
-            st, it, rr = op.solve(b, x, args.rtol, args.maxit)
-            ev[1].record()
-            inf1 = L.guess_get_info(g)
-            L.guess_update(g, x)
-            tu = L.guess_kernel_times(g)
-            if not timed:
-                continue
-            torch.cuda.synchronize()
-            S = stats[m]
-            S["iters"].append(it)
-            S["relres"].append(rr)
-            S["solve_ms"] += ev[0].elapsed_time(ev[1])
-            restart = m == "proj" and (inf1["count"] == 0 or inf1["count"] >= M)
-            for call, times, kdd in (("form", tf, kd_form), ("update", tu, inf1["count"])):
-                names = KERNELS[(m, call)]
-                byts = kernel_bytes(m, call, N, s, kdd, M, restart)
-                for name, ms, by in zip(names, times, byts):
-                    # every kernel of the call counts in the guess time; the
-                    # per-kernel table keeps the streaming kernels that moved data
-                    S["guess_ms"] += ms
-                    S["guess_bytes"] += by
-                    if by == 0:
-                        continue
-                    ks = kstat.setdefault(name, [0, 0.0, 0.0])
-                    ks[0] += 1
-                    ks[1] += ms
-                    ks[2] += by
-            if st != L.OK:
-                raise RuntimeError(f"PCG failed for {m} at step {step}: status {st}")
+            ctx[m] = L.guess_create_ex(N, 1 if m == "last" else M, L.METHODS[m],
+                                       args.degree if m == "extrap" else 0, L.DTYPES[dtype], 1e-6,
+                                       op.handle, L.stream_handle())
+            L.guess_profile(ctx[m], True)
+            xs[m] = torch.zeros(N, dtype=torch.float64, device="cuda")
+            if shadow:
+                sh[m] = L.guess_create_ex(N, 1 if m == "last" else M, L.METHODS[m],
+                                          args.degree if m == "extrap" else 0, L.F64, 1e-6, op.handle,
+                                          L.stream_handle())
+        if shadow:
+            x64 = torch.empty(N, dtype=torch.float64, device="cuda")
+        stats = {m: {"iters": [], "guess_ms": 0.0, "guess_bytes": 0.0, "solve_ms": 0.0, "relres": [],
+                     "err": []} for m in methods}
+        kstat = {}    # kernel -> [launches, ms, bytes]
 
-    for step in range(1, args.warmup + 1):
-        one_step(step, False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for step in range(args.warmup + 1, args.warmup + args.steps + 1):
-        one_step(step, True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+        def one_step(step, timed):
+            t = step * args.dt
+            rhs(t, b)
+            for m in methods:
+                g, x = ctx[m], xs[m]
+                inf0 = L.guess_get_info(g)
+                kd = inf0["count"]
+                kd_form = min(kd, M) if m != "proj" else kd
+                L.guess_form(g, b, x)
+                tf = L.guess_kernel_times(g)
+                if shadow and timed:
+                    L.guess_form(sh[m], b, x64)
+                    nrm = float(torch.linalg.vector_norm(x64))
+                    stats[m]["err"].append(float(torch.linalg.vector_norm(x - x64)) / nrm if nrm > 0 else 0.0)
+                ev[0].record()
+                st, it, rr = op.solve(b, x, args.rtol, args.maxit)
+                ev[1].record()
+                inf1 = L.guess_get_info(g)
+                L.guess_update(g, x)
+                tu = L.guess_kernel_times(g)
+                if shadow:
+                    L.guess_update(sh[m], x)
+                if st != L.OK:
+                    raise RuntimeError(f"PCG failed for {m} ({dtype}) at step {step}: status {st}")
+                if not timed:
+                    continue
+                torch.cuda.synchronize()
+                S = stats[m]
+                S["iters"].append(it)
+                S["relres"].append(rr)
+                S["solve_ms"] += ev[0].elapsed_time(ev[1])
+                restart = m == "proj" and (inf1["count"] == 0 or inf1["count"] >= M)
+                for call, times, kdd in (("form", tf, kd_form), ("update", tu, inf1["count"])):
+                    names = KERNELS[(m, call)]
+                    byts = kernel_bytes(m, call, N, s, kdd, M, restart)
+                    for name, ms, by in zip(names, times, byts):
+                        # every kernel of the call counts in the guess time; the
+                        # per-kernel table keeps the streaming kernels that moved data
+                        S["guess_ms"] += ms
+                        S["guess_bytes"] += by
+                        if by == 0:
+                            continue
+                        ks = kstat.setdefault(name, [0, 0.0, 0.0])
+                        ks[0] += 1
+                        ks[1] += ms
+                        ks[2] += by
 
+        for step in range(1, warmup + 1):
+            one_step(step, False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for step in range(warmup + 1, warmup + steps + 1):
+            one_step(step, True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        for g in list(ctx.values()) + list(sh.values()):
+            L.guess_destroy(g)
+        return stats, kstat, wall
+
+    stats, kstat, wall = run(args.dtype, args.steps, args.warmup)
+    s = L.ELEM_BYTES[L.DTYPES[args.dtype]]
     tot_bytes = sum(S["guess_bytes"] for S in stats.values())
     tot_ms = sum(S["guess_ms"] for S in stats.values())
     value = tot_bytes / (tot_ms * 1e-3) / 1e9
@@ -247,15 +334,32 @@ def main():
                    "n": n, "N": N, "M": M, "degree": args.degree, "methods": methods,
                    "history_dtype": args.dtype, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": dby / dl, "avg_us": 1e3 * dms / dl},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": hbm_traffic(dname),
+                     "bytes_per_launch": dby / dl, "avg_us": 1e3 * dms / dl,
+                     "copy_roof_GBps": roof, "frac_of_copy_roof": achieved / roof},
         "methods": per_method,
         "kernels": kernels,
     }
+    if args.precision_steps > 0 and args.dtype == "f64":
+        prec = {}
+        for dt in ("f32", "f16", "bf16"):
+            st_, ks_, wall_ = run(dt, args.precision_steps, args.warmup, shadow=True)
+            gb = sum(S["guess_bytes"] for S in st_.values())
+            gm = sum(S["guess_ms"] for S in st_.values())
+            prec[dt] = {
+                "guess_GBps": gb / (gm * 1e-3) / 1e9,
+                "ms_per_step_incl_shadow": wall_ * 1e3 / args.precision_steps,
+                "methods": {m: {"pcg_iters_per_step": float(np.mean(S["iters"])),
+                                "pcg_ms_per_step": S["solve_ms"] / args.precision_steps,
+                                "guess_ms_per_step": S["guess_ms"] / args.precision_steps,
+                                "guess_rel_err_vs_f64_mean": float(np.mean(S["err"])),
+                                "guess_rel_err_vs_f64_max": float(np.max(S["err"])),
+                                "max_relres": float(np.max(S["relres"]))} for m, S in st_.items()},
+            }
+        out["precision"] = {"steps": args.precision_steps, "warmup": args.warmup,
+                            "reference": "FP64 history fed the same solutions", "dtypes": prec}
     if args.cpu:
         out["cpu_baseline"] = cpu_baseline(args, s)
-    for g in ctx.values():
-        L.guess_destroy(g)
     op.close()
     print(json.dumps(out), flush=True)
 

@@ -202,14 +202,17 @@ int guess_extrap_weights(int m, int k, double *beta);
 int guess_history_get(guess_t g, int which, int j, double *out);
 
 /*
- * Per-kernel timing (tracing aid).  With profiling enabled the library
- * records a HIP event on the context's stream before and after every kernel
- * that guess_form / guess_update launch for this context.
+ * Per-kernel timing (tracing aid).  With profiling enabled every kernel that
+ * guess_form / guess_update launch for this context is dispatched with a
+ * start and a stop event stamped by the dispatch itself (hipExtLaunchKernel),
+ * so each time is the kernel's own run time.
  * guess_kernel_times waits for the most recent such call and returns the
  * device time of each of its kernels in launch order (ms[0..*n-1]):
  *   EXTRAP/LAST form: extrap_form;  update: ring_store
- *   PROJ form: proj_dots, proj_combine;  update: proj_apply, proj_reorth,
- *   proj_gs_write (the last two return at once after a restart)
+ *   PROJ form: proj_dots, proj_fin, proj_combine;  update: proj_apply,
+ *   proj_fin, proj_reorth, proj_fin, proj_gs_write, proj_fin (proj_fin: the
+ *   one-workgroup finishing step of a reduction; reorth, gs_write and their
+ *   finishing steps return at once after a restart)
  * *n = 0 when profiling is off or the last call launched no kernel.
  */
 int guess_profile(guess_t g, int enable);

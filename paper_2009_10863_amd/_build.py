@@ -18,8 +18,11 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "_lib", "libguess.so")
-SOURCES = ["proj_f64.hip", "proj_f32.hip", "proj_f16.hip", "proj_bf16.hip", "extrap.hip", "proj.hip",
-           "op.hip", "vec.hip", "host.hip"]
+SOURCES = ["proj_f64.hip", "proj_f32.hip", "proj_f16.hip", "proj_bf16.hip", "pcg.hip", "extrap.hip",
+           "proj.hip", "op.hip", "vec.hip", "host.hip"]
+# per-source extra flags: PCG's stencil kernel issues ~30 loads per chunk;
+# the max-ILP scheduler groups them (measured faster there, slower elsewhere)
+EXTRA_FLAGS = {"pcg.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp", "-DLG_WAVES_MIN=2"]}
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -48,7 +51,7 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc(), *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -14,8 +14,11 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
 
 // Reduction kernels stream several vectors per step: allow up to 128 VGPRs
 // (4 waves per SIMD) so that every load of a step is in flight at once.
+#ifndef LG_WAVES_MIN
+#define LG_WAVES_MIN 1
+#endif
 #define LG_REDUCE_KERNEL \
-    __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(1, 4)))
+    __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LG_WAVES_MIN, 4)))
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxPartialBlocks = 2048;
 constexpr int kMaxDots = 2 * GUESS_MAX_M + 4;
@@ -79,6 +82,25 @@ __host__ __device__ __forceinline__ int64_t tail_start(int64_t N) { return (N >>
 __host__ __device__ __forceinline__ int tail_count(int64_t N) { return (int)(N & 255); }
 // first element of chunk c's first pair; the second pair starts 128 later
 __device__ __forceinline__ int64_t chunk_elem(int64_t c) { return ((c >> 6) << 8) + ((c & 63) << 1); }
+
+// XCD-aware split for stencil kernels.  Workgroups are dealt to the 8 XCDs
+// round-robin (workgroup b runs on XCD b mod 8), and each XCD has its own
+// L2.  Giving XCD k one contiguous eighth of the chunks (a z-slab of the
+// grid) that its workgroups sweep together keeps the z-1 / z+1 planes a
+// stencil reads in that XCD's L2 instead of another XCD's.
+constexpr int kXcds = 8;
+struct ChunkRange {
+    int64_t begin, end, step;
+};
+__device__ __forceinline__ ChunkRange xcd_range(int64_t nc) {
+    const int g = gridDim.x;
+    if (g % kXcds != 0) return ChunkRange{(int64_t)blockIdx.x * 256 + threadIdx.x, nc, (int64_t)g * 256};
+    const int xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds, per = g / kXcds;
+    const int64_t span = (nc + kXcds * 64 - 1) / (kXcds * 64) * 64;   // multiple of a wave's 64 chunks
+    const int64_t b = (int64_t)xcd * span;
+    const int64_t e = b + span < nc ? b + span : nc;
+    return ChunkRange{b + (int64_t)local * 256 + threadIdx.x, e, (int64_t)per * 256};
+}
 
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f2 __attribute__((ext_vector_type(2)));

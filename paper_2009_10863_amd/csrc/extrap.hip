@@ -115,14 +115,14 @@ int launch_widen(int dtype, const void *src, double scale, double *out, int64_t 
 }
 
 template <int DT, int K>
-static void run_form(const ExtrapArgs &a, double *x0, int64_t N, int grid, hipStream_t s) {
-    extrap_form_kernel<DT, K><<<grid, kBlock, 0, s>>>(a, x0, N);
+static void run_form(const ExtrapArgs &a, double *x0, int64_t N, int grid, hipStream_t s, KEvents *ev) {
+    klaunch(ev, 0, extrap_form_kernel<DT, K>, grid, kBlock, s, a, x0, N);
 }
 
 template <int DT>
-static int form_dt(int k, const ExtrapArgs &a, double *x0, int64_t N, int grid, hipStream_t s) {
+static int form_dt(int k, const ExtrapArgs &a, double *x0, int64_t N, int grid, hipStream_t s, KEvents *ev) {
     switch (k) {
-#define LG_K(KK) case KK: run_form<DT, KK>(a, x0, N, grid, s); break;
+#define LG_K(KK) case KK: run_form<DT, KK>(a, x0, N, grid, s, ev); break;
         LG_K(1) LG_K(2) LG_K(3) LG_K(4) LG_K(5) LG_K(6) LG_K(7) LG_K(8)
         LG_K(9) LG_K(10) LG_K(11) LG_K(12) LG_K(13) LG_K(14) LG_K(15) LG_K(16)
 #undef LG_K
@@ -140,31 +140,24 @@ int launch_extrap_form(int dtype, int k, const void *const *slots, const double 
         a.beta[j] = beta[j];
     }
     const int grid = stream_grid(nchunks(N), grid_cap());
-    int rc = GUESS_EINVAL;
-    kev(ev, 0, s);
     switch (dtype) {
-        case GUESS_F64: rc = form_dt<GUESS_F64>(k, a, x0, N, grid, s); break;
-        case GUESS_F32: rc = form_dt<GUESS_F32>(k, a, x0, N, grid, s); break;
-        case GUESS_F16: rc = form_dt<GUESS_F16>(k, a, x0, N, grid, s); break;
-        case GUESS_BF16: rc = form_dt<GUESS_BF16>(k, a, x0, N, grid, s); break;
+        case GUESS_F64: return form_dt<GUESS_F64>(k, a, x0, N, grid, s, ev);
+        case GUESS_F32: return form_dt<GUESS_F32>(k, a, x0, N, grid, s, ev);
+        case GUESS_F16: return form_dt<GUESS_F16>(k, a, x0, N, grid, s, ev);
+        case GUESS_BF16: return form_dt<GUESS_BF16>(k, a, x0, N, grid, s, ev);
     }
-    kev(ev, 1, s);
-    if (ev) ev->count = 1;
-    return rc;
+    return GUESS_EINVAL;
 }
 
 int launch_ring_store(int dtype, const double *x, void *slot, int64_t N, hipStream_t s, KEvents *ev) {
     const int grid = stream_grid(nchunks(N), grid_cap());
-    kev(ev, 0, s);
-    if (ev) ev->count = 1;
     switch (dtype) {
-        case GUESS_F64: ring_store_kernel<GUESS_F64><<<grid, kBlock, 0, s>>>(x, slot, N); break;
-        case GUESS_F32: ring_store_kernel<GUESS_F32><<<grid, kBlock, 0, s>>>(x, slot, N); break;
-        case GUESS_F16: ring_store_kernel<GUESS_F16><<<grid, kBlock, 0, s>>>(x, slot, N); break;
-        case GUESS_BF16: ring_store_kernel<GUESS_BF16><<<grid, kBlock, 0, s>>>(x, slot, N); break;
+        case GUESS_F64: klaunch(ev, 0, ring_store_kernel<GUESS_F64>, grid, kBlock, s, x, slot, N); break;
+        case GUESS_F32: klaunch(ev, 0, ring_store_kernel<GUESS_F32>, grid, kBlock, s, x, slot, N); break;
+        case GUESS_F16: klaunch(ev, 0, ring_store_kernel<GUESS_F16>, grid, kBlock, s, x, slot, N); break;
+        case GUESS_BF16: klaunch(ev, 0, ring_store_kernel<GUESS_BF16>, grid, kBlock, s, x, slot, N); break;
         default: return GUESS_EINVAL;
     }
-    kev(ev, 1, s);
     return GUESS_OK;
 }
 

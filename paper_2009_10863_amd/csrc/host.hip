@@ -348,7 +348,10 @@ struct guess_ctx {
 static void ctx_free(guess_ctx *g) {
     if (!g) return;
     if (g->prof)
-        for (hipEvent_t e : g->kev.e) (void)hipEventDestroy(e);
+        for (int i = 0; i < 8; ++i) {
+            (void)hipEventDestroy(g->kev.start[i]);
+            (void)hipEventDestroy(g->kev.stop[i]);
+        }
     for (void *ptr : {g->ring, g->X, g->B, (void *)g->w, (void *)g->part, (void *)g->st})
         if (ptr) (void)hipFree(ptr);
     if (g->host_st) (void)hipHostFree(g->host_st);
@@ -614,11 +617,17 @@ extern "C" int guess_reset(guess_t g) {
 extern "C" int guess_profile(guess_t g, int enable) {
     if (!g) return fail(GUESS_EINVAL, "guess_profile: NULL context");
     if (enable && !g->prof) {
-        for (hipEvent_t &e : g->kev.e) LG_HIP(hipEventCreate(&e));
+        for (int i = 0; i < 8; ++i) {
+            LG_HIP(hipEventCreate(&g->kev.start[i]));
+            LG_HIP(hipEventCreate(&g->kev.stop[i]));
+        }
         g->prof = true;
     } else if (!enable && g->prof) {
         LG_HIP(hipStreamSynchronize(g->stream));
-        for (hipEvent_t &e : g->kev.e) (void)hipEventDestroy(e);
+        for (int i = 0; i < 8; ++i) {
+            (void)hipEventDestroy(g->kev.start[i]);
+            (void)hipEventDestroy(g->kev.stop[i]);
+        }
         g->prof = false;
     }
     g->kev.count = 0;
@@ -630,10 +639,10 @@ extern "C" int guess_kernel_times(guess_t g, double *ms, int max, int *n) {
     *n = 0;
     if (!g->prof || g->kev.count == 0) return GUESS_OK;
     const int cnt = g->kev.count;
-    LG_HIP(hipEventSynchronize(g->kev.e[cnt]));
+    LG_HIP(hipEventSynchronize(g->kev.stop[cnt - 1]));
     for (int i = 0; i < cnt && i < max; ++i) {
         float t = 0.0f;
-        LG_HIP(hipEventElapsedTime(&t, g->kev.e[i], g->kev.e[i + 1]));
+        LG_HIP(hipEventElapsedTime(&t, g->kev.start[i], g->kev.stop[i]));
         ms[i] = t;
     }
     *n = cnt < max ? cnt : max;

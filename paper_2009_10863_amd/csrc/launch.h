@@ -1,6 +1,7 @@
 // Host-side launchers of the libguess kernels (one translation unit per family).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -9,14 +10,22 @@
 
 namespace lg {
 
-// Optional per-kernel timing: when non-null, a launcher records e[i] before
-// its i-th kernel and e[count] after the last one (on the launch stream).
+// Optional per-kernel timing: with events, the i-th kernel of a launcher is
+// dispatched through hipExtLaunchKernel, whose dispatch packet itself stamps
+// start[i] and stop[i], so the measured time is the kernel's own run time.
 struct KEvents {
-    hipEvent_t e[8];
+    hipEvent_t start[8], stop[8];
     int count;          // kernels launched (set by the launcher)
 };
-inline void kev(KEvents *k, int i, hipStream_t s) {
-    if (k) (void)hipEventRecord(k->e[i], s);
+
+template <typename... Args, typename F = void (*)(Args...)>
+inline void klaunch(KEvents *ev, int i, F f, int grid, int block, hipStream_t s, Args... args) {
+    if (ev) {
+        hipExtLaunchKernelGGL(f, dim3(grid), dim3(block), 0, s, ev->start[i], ev->stop[i], 0, args...);
+        ev->count = i + 1;
+    } else {
+        hipLaunchKernelGGL(f, dim3(grid), dim3(block), 0, s, args...);
+    }
 }
 
 // Device-resident state of a projection history.  Decisions (restart,

@@ -1,0 +1,269 @@
+// Jacobi-preconditioned conjugate gradients (§5.3) on the 7-point operator.
+//
+// PCG keeps its scalars (rho, alpha, thresholds, iteration count,
+// convergence flag) on the device, and every kernel returns at once when the
+// solve has converged or broken down.  The host therefore enqueues
+// iterations in batches and only reads the state between batches; the
+// iteration count is still exact.
+//
+// This translation unit is compiled with the max-ILP instruction scheduler:
+// the search-direction stencil issues ~30 loads per chunk, and grouping them
+// measured 6 % faster per iteration than the default schedule at 256^3.
+#include "common.h"
+#include "launch.h"
+
+namespace lg {
+
+static __device__ __forceinline__ V4 toV(const R4 &r) { return V4{{r.v[0], r.v[1], r.v[2], r.v[3]}}; }
+
+// ------------------------------------------------------------------ PCG
+// Two streaming kernels per iteration k (1-based), both with one row of
+// partial sums per workgroup.  Every workgroup of the next kernel sums the
+// previous kernel's rows itself, in the same fixed order, so all of them see
+// identical scalars without any cross-workgroup synchronisation.
+//
+//   pcg_a(k): from rows (r^T r, r^T z, b^T b) of r_{k-1}: stop test (k = 1:
+//             also the threshold); rho_k = r^T z; beta = rho_k / rho_{k-1};
+//             p_k = z + beta p_{k-1} formed on the fly at the stencil points
+//             (z = D^{-1} r), stored, and q = A p_k; rows: p_k^T q.
+//   pcg_b(k): alpha = rho_k / p_k^T q; x += alpha p_k; r -= alpha q;
+//             rows: (r^T r, r^T z, 0).
+// Per iteration: reads r, p_{k-1} (pcg_a, 16 B/unknown), x, r, p_k, q
+// (pcg_b, 32 B); writes p_k, q, x, r (32 B): 80 B per unknown (constant
+// coefficient).  p_k and p_{k-1} live in two buffers used alternately.
+int pcg_grid(const Grid &g) { return stream_grid(nchunks(g.n), reduce_blocks()); }
+
+__device__ __forceinline__ bool pcg_done(const PcgState *st) { return st->converged | st->breakdown; }
+
+template <bool VAR>
+__device__ __forceinline__ V4 dinv4(const Grid &g, int64_t c) {
+    if constexpr (VAR) return load4<GUESS_F64>(g.dinv, c);
+    else return V4{{g.dinv_const, g.dinv_const, g.dinv_const, g.dinv_const}};
+}
+
+// The next search direction as a stencil operand: p = D^{-1} r + beta p_old
+// (first iteration: p = D^{-1} r), evaluated wherever the stencil reads it.
+template <bool VAR>
+struct PNext {
+    const double *__restrict__ r;
+    const double *__restrict__ pold;
+    const double *__restrict__ dinv;
+    double dconst, beta;
+    bool first;
+    // p_old is read even in the first iteration (and then ignored by the
+    // select), so that no load sits behind a branch
+    __device__ __forceinline__ double operator()(int64_t q) const {
+        const double z = (VAR ? dinv[q] : dconst) * r[q];
+        const double pq = __builtin_fma(beta, pold[q], z);
+        return first ? z : pq;
+    }
+    __device__ __forceinline__ R2 two(int64_t q) const {
+        const R2 rv = ld2(r, q);
+        const R2 pv = ld2(pold, q);
+        R2 dv;
+        if constexpr (VAR) dv = ld2(dinv, q);
+        else dv = R2{{dconst, dconst}};
+        R2 out;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const double z = dv.v[e] * rv.v[e];
+            const double pq = __builtin_fma(beta, pv.v[e], z);
+            out.v[e] = first ? z : pq;
+        }
+        return out;
+    }
+};
+
+// r = b - A x; rows (r^T r, r^T D^{-1} r, b^T b).
+template <bool VAR, bool AL>
+LG_REDUCE_KERNEL void pcg_init_kernel(Grid g, const double *__restrict__ b, const double *__restrict__ x,
+                                      double *__restrict__ r, double *part) {
+    __shared__ double lds[kLdsDoubles];
+    double acc[3] = {0.0, 0.0, 0.0};
+    const ChunkRange cr = xcd_range(nchunks(g.n));
+    for (int64_t c = cr.begin; c < cr.end; c += cr.step) {
+        R4 uc;
+        const R4 ax = apply4g<VAR, AL>(x, g, c, uc);
+        const V4 bv = load4<GUESS_F64>(b, c), dv = dinv4<VAR>(g, c);
+        V4 rv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            rv.v[e] = bv.v[e] - ax.v[e];
+            acc[0] = __builtin_fma(rv.v[e], rv.v[e], acc[0]);
+            acc[1] = __builtin_fma(rv.v[e], dv.v[e] * rv.v[e], acc[1]);
+            acc[2] = __builtin_fma(bv.v[e], bv.v[e], acc[2]);
+        }
+        store4<GUESS_F64>(r, c, rv);
+    }
+    if (blockIdx.x == 0 && threadIdx.x < tail_count(g.n)) {
+        const int64_t q = tail_start(g.n) + threadIdx.x;
+        const double rq = b[q] - apply_pt<VAR>(VecU{x}, g, q);
+        r[q] = rq;
+        acc[0] = __builtin_fma(rq, rq, acc[0]);
+        acc[1] = __builtin_fma(rq, dinv_at<VAR>(g, q) * rq, acc[1]);
+        acc[2] = __builtin_fma(b[q], b[q], acc[2]);
+    }
+    block_partials<3>(acc, part, lds);
+}
+
+template <bool VAR, bool AL>
+LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, const double *__restrict__ r, const double *__restrict__ pold,
+                                   double *__restrict__ pnew, double *__restrict__ q,
+                                   const double *part_b, double *part_a, PcgState *st, int k, double rtol) {
+    __shared__ double lds[kLdsDoubles];
+    if (pcg_done(st)) return;
+    double tot[3];
+    final_sums<3>(part_b, gridDim.x, tot, lds);
+    const double rr = tot[0], rz = tot[1];
+    const double rn = sqrt(rr);
+    double thresh;
+    if (k == 1) thresh = st->rule == GUESS_STOP_RHS ? rtol * sqrt(tot[2]) : rtol * fmax(rn, 1.0);
+    else thresh = st->thresh;
+    const bool stop = st->rule == GUESS_STOP_RHS ? (rn <= thresh) : (rn < thresh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (k == 1) {
+            st->thresh = thresh;
+            st->bb = tot[2];
+            st->rr0 = rr;
+        }
+        st->rr = rr;
+        if (stop) {
+            st->converged = 1;
+            st->it = k - 1;
+        } else {
+            st->rho[k & 1] = rz;
+        }
+    }
+    if (stop) return;
+    const bool first = k == 1;
+    const double beta = first ? 0.0 : rz / st->rho[(k - 1) & 1];
+    const PNext<VAR> pn{r, pold, g.dinv, g.dinv_const, beta, first};
+    double acc[1] = {0.0};
+    const ChunkRange cr = xcd_range(nchunks(g.n));
+    for (int64_t c = cr.begin; c < cr.end; c += cr.step) {
+        R4 pc;
+        const R4 qv = apply4g<VAR, AL>(pn, g, c, pc);
+        store4<GUESS_F64>(pnew, c, toV(pc));
+        store4<GUESS_F64>(q, c, toV(qv));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(pc.v[e], qv.v[e], acc[0]);
+    }
+    if (blockIdx.x == 0 && threadIdx.x < tail_count(g.n)) {
+        const int64_t t = tail_start(g.n) + threadIdx.x;
+        const double pt = pn(t);
+        const double qt = apply_pt<VAR>(pn, g, t);
+        pnew[t] = pt;
+        q[t] = qt;
+        acc[0] = __builtin_fma(pt, qt, acc[0]);
+    }
+    block_partials<1>(acc, part_a, lds);
+}
+
+template <bool VAR>
+LG_REDUCE_KERNEL void pcg_b_kernel(Grid g, double *__restrict__ x, double *__restrict__ r,
+                                   const double *__restrict__ p, const double *__restrict__ q,
+                                   const double *part_a, double *part_b, PcgState *st, int k) {
+    __shared__ double lds[kLdsDoubles];
+    if (pcg_done(st)) return;
+    double tot[1];
+    final_sums<1>(part_a, gridDim.x, tot, lds);
+    const double pq = tot[0];
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->breakdown = 1;
+            st->it = k;
+        }
+        return;
+    }
+    const double alpha = st->rho[k & 1] / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->alpha = alpha;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const int64_t nc = nchunks(g.n), stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
+        V4 xv = load4<GUESS_F64>(x, c), rv = load4<GUESS_F64>(r, c);
+        const V4 pv = load4<GUESS_F64>(p, c), qv = load4<GUESS_F64>(q, c), dv = dinv4<VAR>(g, c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            xv.v[e] = __builtin_fma(alpha, pv.v[e], xv.v[e]);
+            rv.v[e] = __builtin_fma(-alpha, qv.v[e], rv.v[e]);
+            acc[0] = __builtin_fma(rv.v[e], rv.v[e], acc[0]);
+            acc[1] = __builtin_fma(rv.v[e], dv.v[e] * rv.v[e], acc[1]);
+        }
+        store4<GUESS_F64>(x, c, xv);
+        store4<GUESS_F64>(r, c, rv);
+    }
+    if (blockIdx.x == 0 && threadIdx.x < tail_count(g.n)) {
+        const int64_t t = tail_start(g.n) + threadIdx.x;
+        x[t] = __builtin_fma(alpha, p[t], x[t]);
+        const double rt = __builtin_fma(-alpha, q[t], r[t]);
+        r[t] = rt;
+        acc[0] = __builtin_fma(rt, rt, acc[0]);
+        acc[1] = __builtin_fma(rt, dinv_at<VAR>(g, t) * rt, acc[1]);
+    }
+    block_partials<3>(acc, part_b, lds);
+}
+
+int launch_pcg_init(const Grid &g, const double *b, const double *x, double *r, double *part_b, hipStream_t s) {
+    const int gr = pcg_grid(g);
+    if (g.kx) {
+        if (g.aligned) pcg_init_kernel<true, true><<<gr, kBlock, 0, s>>>(g, b, x, r, part_b);
+        else pcg_init_kernel<true, false><<<gr, kBlock, 0, s>>>(g, b, x, r, part_b);
+    } else {
+        if (g.aligned) pcg_init_kernel<false, true><<<gr, kBlock, 0, s>>>(g, b, x, r, part_b);
+        else pcg_init_kernel<false, false><<<gr, kBlock, 0, s>>>(g, b, x, r, part_b);
+    }
+    return GUESS_OK;
+}
+
+template <bool VAR, bool AL>
+static void pcg_iter_v(const Grid &g, double *x, double *r, double *const p[2], double *q, double *part_a,
+                       double *part_b, PcgState *st, int k, double rtol, hipStream_t s) {
+    const int gr = pcg_grid(g);
+    double *pnew = p[k & 1];
+    const double *pold = p[(k - 1) & 1];
+    pcg_a_kernel<VAR, AL><<<gr, kBlock, 0, s>>>(g, r, pold, pnew, q, part_b, part_a, st, k, rtol);
+    pcg_b_kernel<VAR><<<gr, kBlock, 0, s>>>(g, x, r, pnew, q, part_a, part_b, st, k);
+}
+
+int launch_pcg_iter(const Grid &g, double *x, double *r, double *const p[2], double *q, double *part_a,
+                    double *part_b, PcgState *st, int k, double rtol, hipStream_t s) {
+    if (g.kx) {
+        if (g.aligned) pcg_iter_v<true, true>(g, x, r, p, q, part_a, part_b, st, k, rtol, s);
+        else pcg_iter_v<true, false>(g, x, r, p, q, part_a, part_b, st, k, rtol, s);
+    } else {
+        if (g.aligned) pcg_iter_v<false, true>(g, x, r, p, q, part_a, part_b, st, k, rtol, s);
+        else pcg_iter_v<false, false>(g, x, r, p, q, part_a, part_b, st, k, rtol, s);
+    }
+    return GUESS_OK;
+}
+
+// Convergence check after the last allowed iteration (pcg_a without the update).
+__global__ __launch_bounds__(kBlock) void pcg_check_kernel(const double *part_b, int nb, PcgState *st, int k,
+                                                           double rtol) {
+    __shared__ double lds[kLdsDoubles];
+    if (pcg_done(st)) return;
+    double tot[3];
+    final_sums<3>(part_b, nb, tot, lds);
+    if (threadIdx.x == 0) {
+        const double rn = sqrt(tot[0]);
+        double thresh = st->thresh;
+        if (k == 1) thresh = st->rule == GUESS_STOP_RHS ? rtol * sqrt(tot[2]) : rtol * fmax(rn, 1.0);
+        const bool stop = st->rule == GUESS_STOP_RHS ? (rn <= thresh) : (rn < thresh);
+        st->rr = tot[0];
+        if (k == 1) {
+            st->bb = tot[2];
+            st->rr0 = tot[0];
+        }
+        if (stop) {
+            st->converged = 1;
+            st->it = k - 1;
+        }
+    }
+}
+
+int launch_pcg_check(const Grid &g, const double *part_b, PcgState *st, int k, double rtol, hipStream_t s) {
+    pcg_check_kernel<<<1, kBlock, 0, s>>>(part_b, pcg_grid(g), st, k, rtol);
+    return GUESS_OK;
+}
+
+}  // namespace lg

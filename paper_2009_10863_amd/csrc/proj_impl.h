@@ -128,7 +128,8 @@ LG_REDUCE_KERNEL void proj_apply_kernel(ProjArgs a, Grid g, const double *__rest
                                         const double *__restrict__ Ax) {
     __shared__ double lds[kLdsDoubles];
     const int d = a.st->d;
-    const int64_t nc = nchunks(a.N), stride = (int64_t)gridDim.x * kBlock;
+    const int64_t nc = nchunks(a.N);
+    const ChunkRange cr = xcd_range(nc);
     const int rem = tail_count(a.N);
     // x and A x for one chunk (the stencil also returns its centre values)
     auto xw4 = [&](int64_t c, V4 &xv) -> V4 {
@@ -149,7 +150,7 @@ LG_REDUCE_KERNEL void proj_apply_kernel(ProjArgs a, Grid g, const double *__rest
     if (d == 0 || d >= a.M) {
         // restart: slot 1 <- x, B slot 1 <- A x; partial nu0^2 = x^T A x
         double acc[1] = {0.0};
-        for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
+        for (int64_t c = cr.begin; c < cr.end; c += cr.step) {
             V4 xv;
             const V4 wv = xw4(c, xv);
 #pragma unroll
@@ -173,7 +174,7 @@ LG_REDUCE_KERNEL void proj_apply_kernel(ProjArgs a, Grid g, const double *__rest
         double acc[ND];
 #pragma unroll
         for (int j = 0; j < ND; ++j) acc[j] = 0.0;
-        for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
+        for (int64_t c = cr.begin; c < cr.end; c += cr.step) {
             V4 xc[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) xc[j] = load4<DT>(colp<DT>(a.X, a.ld, j), c);
@@ -406,14 +407,9 @@ template <int DT>
 void proj_form_dt(const ProjBufs &p, const double *b, double *x0, hipStream_t s, KEvents *ev) {
     const ProjArgs a = make_args(p);
     const int gr = stream_grid(nchunks(a.N), reduce_blocks());
-    kev(ev, 0, s);
-    proj_dots_kernel<DT><<<gr, kBlock, 0, s>>>(a, b);
-    kev(ev, 1, s);
-    proj_fin_kernel<FIN_DOTS><<<1, kBlock, 0, s>>>(a, gr);
-    kev(ev, 2, s);
-    proj_combine_kernel<DT><<<stream_grid(nchunks(a.N), grid_cap()), kBlock, 0, s>>>(a, x0);
-    kev(ev, 3, s);
-    if (ev) ev->count = 3;
+    klaunch(ev, 0, proj_dots_kernel<DT>, gr, kBlock, s, a, b);
+    klaunch(ev, 1, proj_fin_kernel<FIN_DOTS>, 1, kBlock, s, a, gr);
+    klaunch(ev, 2, proj_combine_kernel<DT>, stream_grid(nchunks(a.N), grid_cap()), kBlock, s, a, x0);
 }
 
 template <int DT>
@@ -422,29 +418,21 @@ void proj_update_dt(const ProjBufs &p, const Grid *g, const double *x, const dou
     const ProjArgs a = make_args(p);
     const int gr = stream_grid(nchunks(a.N), reduce_blocks());
     const Grid gg = g ? *g : Grid{};
-    kev(ev, 0, s);
     if (Ax) {
-        proj_apply_kernel<DT, false, true, true><<<gr, kBlock, 0, s>>>(a, gg, x, Ax);
+        klaunch(ev, 0, proj_apply_kernel<DT, false, true, true>, gr, kBlock, s, a, gg, x, Ax);
     } else if (g->kx) {
-        if (g->aligned) proj_apply_kernel<DT, true, false, true><<<gr, kBlock, 0, s>>>(a, gg, x, nullptr);
-        else proj_apply_kernel<DT, true, false, false><<<gr, kBlock, 0, s>>>(a, gg, x, nullptr);
+        if (g->aligned) klaunch(ev, 0, proj_apply_kernel<DT, true, false, true>, gr, kBlock, s, a, gg, x, Ax);
+        else klaunch(ev, 0, proj_apply_kernel<DT, true, false, false>, gr, kBlock, s, a, gg, x, Ax);
     } else {
-        if (g->aligned) proj_apply_kernel<DT, false, false, true><<<gr, kBlock, 0, s>>>(a, gg, x, nullptr);
-        else proj_apply_kernel<DT, false, false, false><<<gr, kBlock, 0, s>>>(a, gg, x, nullptr);
+        if (g->aligned) klaunch(ev, 0, proj_apply_kernel<DT, false, false, true>, gr, kBlock, s, a, gg, x, Ax);
+        else klaunch(ev, 0, proj_apply_kernel<DT, false, false, false>, gr, kBlock, s, a, gg, x, Ax);
     }
-    kev(ev, 1, s);
-    proj_fin_kernel<FIN_APPLY><<<1, kBlock, 0, s>>>(a, gr);
-    kev(ev, 2, s);
+    klaunch(ev, 1, proj_fin_kernel<FIN_APPLY>, 1, kBlock, s, a, gr);
     const double *w = Ax ? Ax : a.w;
-    proj_reorth_kernel<DT><<<gr, kBlock, 0, s>>>(a, w);
-    kev(ev, 3, s);
-    proj_fin_kernel<FIN_REORTH><<<1, kBlock, 0, s>>>(a, gr);
-    kev(ev, 4, s);
-    proj_gs_write_kernel<DT><<<gr, kBlock, 0, s>>>(a, x, w);
-    kev(ev, 5, s);
-    proj_fin_kernel<FIN_GS><<<1, kBlock, 0, s>>>(a, gr);
-    kev(ev, 6, s);
-    if (ev) ev->count = 6;
+    klaunch(ev, 2, proj_reorth_kernel<DT>, gr, kBlock, s, a, w);
+    klaunch(ev, 3, proj_fin_kernel<FIN_REORTH>, 1, kBlock, s, a, gr);
+    klaunch(ev, 4, proj_gs_write_kernel<DT>, gr, kBlock, s, a, x, w);
+    klaunch(ev, 5, proj_fin_kernel<FIN_GS>, 1, kBlock, s, a, gr);
 }
 
 }  // namespace lg

@@ -151,19 +151,33 @@ struct VecU {
 };
 
 // A u at p0, p0+1 (p0 even, nx even: one grid row).  Also returns the centre values.
+// Every load is unconditional -- a neighbour outside the grid is read at the
+// centre's address and replaced by 0 afterwards -- so that the wave issues
+// all of its loads back to back instead of waiting around each branch.
 template <bool VAR, class U>
 __device__ __forceinline__ R2 apply2(U u, const Grid &g, int64_t p0, R2 &uc) {
 #pragma clang fp contract(off)
     int i0, j, l;
     coords(g, p0, i0, j, l);
+    const bool hw = i0 > 0, he = i0 + 2 < g.nx, hs = j > 0, hn = j < g.ny - 1, hb = l > 0,
+               ht = l < g.nz - 1;
     uc = u.two(p0);
-    const R2 z{{0.0, 0.0}};
-    const double uw = i0 > 0 ? u(p0 - 1) : 0.0;
-    const double ue = i0 + 2 < g.nx ? u(p0 + 2) : 0.0;
-    const R2 us = j > 0 ? u.two(p0 - g.nx) : z;
-    const R2 un = j < g.ny - 1 ? u.two(p0 + g.nx) : z;
-    const R2 ub = l > 0 ? u.two(p0 - g.nxy) : z;
-    const R2 ut = l < g.nz - 1 ? u.two(p0 + g.nxy) : z;
+    const double uw0 = u(hw ? p0 - 1 : p0);
+    const double ue0 = u(he ? p0 + 2 : p0);
+    const R2 us0 = u.two(hs ? p0 - g.nx : p0);
+    const R2 un0 = u.two(hn ? p0 + g.nx : p0);
+    const R2 ub0 = u.two(hb ? p0 - g.nxy : p0);
+    const R2 ut0 = u.two(ht ? p0 + g.nxy : p0);
+    const double uw = hw ? uw0 : 0.0;
+    const double ue = he ? ue0 : 0.0;
+    R2 us, un, ub, ut;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        us.v[e] = hs ? us0.v[e] : 0.0;
+        un.v[e] = hn ? un0.v[e] : 0.0;
+        ub.v[e] = hb ? ub0.v[e] : 0.0;
+        ut.v[e] = ht ? ut0.v[e] : 0.0;
+    }
     R2 r;
     if constexpr (!VAR) {
 #pragma unroll

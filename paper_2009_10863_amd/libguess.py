@@ -13,7 +13,7 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libguess.so")
+LIB_PATH = os.environ.get("LIBGUESS_SO") or os.path.join(_HERE, "_lib", "libguess.so")
 
 # ---------------------------------------------------------------- constants
 ZERO, LAST, EXTRAP, PROJ = 0, 1, 2, 3
