@@ -123,7 +123,8 @@ def form(history_oldest_first, beta) -> np.ndarray:
 
 
 class ExtrapHistory:
-    """Last-M-solutions history with least-squares extrapolation (§3.2).
+    """Last-M-solutions history with least-squares extrapolation (§3.2), or
+    with sparse extrapolation (§3.3) when ``sparse`` is set.
 
     ``dtype`` selects the storage format of stored solutions (see
     ``oracle.lowprec``); the guess itself is always evaluated in FP64 from the
@@ -131,10 +132,10 @@ class ExtrapHistory:
     accumulation approximates.
     """
 
-    def __init__(self, M: int, m: int, dtype: str = "f64"):
+    def __init__(self, M: int, m: int, dtype: str = "f64", sparse: bool = False):
         if not (0 <= m <= M - 1):
             raise ValueError("need 0 <= m <= M-1")
-        self.M, self.m, self.dtype = M, m, dtype
+        self.M, self.m, self.dtype, self.sparse = M, m, dtype, sparse
         self.hist = []          # oldest first, stored values as float64 arrays
         self._cache = {}
 
@@ -143,7 +144,7 @@ class ExtrapHistory:
         if p is None:
             return None
         if p not in self._cache:
-            self._cache[p] = to_f64(beta_ls_exact(*p))
+            self._cache[p] = to_f64(beta_sparse_exact(*p) if self.sparse else beta_ls_exact(*p))
         return self._cache[p]
 
     def form(self, b=None, N=None) -> np.ndarray:
@@ -164,3 +165,83 @@ class ExtrapHistory:
 
     def reset(self) -> None:
         self.hist = []
+
+
+# ---------------------------------------------------------------- sparse extrapolation (§3.3)
+def legendre_vandermonde(M: int, m: int):
+    """V_ij = P_j(t_i), v_j = P_j(t_new) with Legendre polynomials P_j (§3.2).
+
+    The paper allows any basis well behaved on [-1, 1]; the least-squares
+    weights do not depend on it, but the nodes chosen by column pivoting do.
+    Reading used here: Legendre, through the three-term recurrence
+    (j+1) P_{j+1} = (2j+1) t P_j - j P_{j-1}, in exact arithmetic.
+    """
+    t, tn = time_nodes(M)
+
+    def P(x):
+        out = [Fraction(1)]
+        if m >= 1:
+            out.append(Fraction(x))
+        for j in range(1, m):
+            out.append(((2 * j + 1) * x * out[j] - j * out[j - 1]) / (j + 1))
+        return out[: m + 1]
+
+    return [P(ti) for ti in t], P(tn)
+
+
+def cpqr_pivots(m: int, M: int):
+    """Column order chosen by column-pivoted QR of V^T (§3.3), first m+1 pivots.
+
+    Column pivoting takes, at each step, the column of V^T (one history node)
+    whose component orthogonal to the columns already taken has the largest
+    norm.  The computation is exact (rational Gram-Schmidt without
+    normalisation, so no square roots); among exactly equal norms the lowest
+    node index wins, the first-maximum rule of LAPACK's pivoting.  Returns
+    0-based node indices in pivot order.
+    """
+    if not (0 <= m <= M - 1):
+        raise ValueError("need 0 <= m <= M-1")
+    V, _ = legendre_vandermonde(M, m)
+    cols = [list(row) for row in V]          # column i of V^T = row i of V
+    basis = []                               # orthogonal (unnormalised) directions taken so far
+    chosen = []
+
+    def residual(c):
+        r = list(c)
+        for q, qq in basis:
+            f = sum(a * b for a, b in zip(r, q)) / qq
+            r = [a - f * b for a, b in zip(r, q)]
+        return r
+
+    for _ in range(m + 1):
+        best, best_i, best_r = None, None, None
+        for i in range(M):
+            if i in chosen:
+                continue
+            r = residual(cols[i])
+            nn = sum(a * a for a in r)
+            if best is None or nn > best:
+                best, best_i, best_r = nn, i, r
+        if best == 0:
+            raise ValueError("V^T is rank deficient")
+        chosen.append(best_i)
+        basis.append((best_r, best))
+    return chosen
+
+
+def beta_sparse_exact(m: int, M: int):
+    """Sparse extrapolation weights (§3.3, eq. CPQRCoeffs) as Fractions.
+
+    With V^T P = Q R and R = [R_hat R_tilde], the weights are
+    beta = P [R_hat^{-1} Q^T v; 0]: the m+1 pivot columns of V^T form the
+    square block Q R_hat, so beta_hat solves (V_S)^T beta_hat = v on the
+    pivot nodes S, and every other weight is zero.
+    """
+    S = cpqr_pivots(m, M)
+    V, v = legendre_vandermonde(M, m)
+    G = [[V[S[c]][r] for c in range(m + 1)] for r in range(m + 1)]     # (V_S)^T
+    bh = _solve_exact(G, v)
+    beta = [Fraction(0)] * M
+    for c, i in enumerate(S):
+        beta[i] = bh[c]
+    return beta

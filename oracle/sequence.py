@@ -12,7 +12,7 @@ import numpy as np
 from .extrap import ExtrapHistory
 from .operator import Operator
 from .pcg import pcg
-from .projection import AOrthoProjection
+from .projection import AOrthoProjection, Projection
 
 
 class ZeroGuess:
@@ -37,8 +37,8 @@ class LastGuess:
 
 
 class ExtrapGuess:
-    def __init__(self, M, m, dtype="f64"):
-        self.h = ExtrapHistory(M, m, dtype)
+    def __init__(self, M, m, dtype="f64", sparse=False):
+        self.h = ExtrapHistory(M, m, dtype, sparse)
 
     def form(self, b, N=None):
         return self.h.form(b, N=len(b))
@@ -54,8 +54,13 @@ def make_guess(method: str, M: int, degree: int, op, eps_rel=1e-6, dtype="f64"):
         return LastGuess(dtype)
     if method == "extrap":
         return ExtrapGuess(M, degree, dtype)
+    if method == "spextrap":
+        return ExtrapGuess(M, degree, dtype, sparse=True)
     if method == "proj":
         return AOrthoProjection(M, op, eps_rel, dtype)
+    if method in ("projqr", "proj_l2", "projqr_l2"):
+        variant = "qr" if method.startswith("projqr") else "classic"
+        return Projection(M, op, eps_rel, dtype, variant, "l2" if method.endswith("_l2") else "A")
     raise ValueError(method)
 
 
