@@ -36,14 +36,19 @@ KERNELS = {
     ("extrap", "update"): ["ring_store"],
     ("last", "form"): ["extrap_form"],
     ("last", "update"): ["ring_store"],
+    ("spextrap", "form"): ["extrap_form"],
+    ("spextrap", "update"): ["ring_store"],
     ("proj", "form"): ["proj_dots", "proj_fin", "proj_combine"],
     ("proj", "update"): ["proj_apply", "proj_fin", "proj_reorth", "proj_fin", "proj_gs_write", "proj_fin"],
 }
+for _m in ("projqr", "proj_l2", "projqr_l2"):
+    KERNELS[(_m, "form")] = KERNELS[("proj", "form")]
+    KERNELS[(_m, "update")] = KERNELS[("proj", "update")]
 
 
 def kernel_bytes(method, call, N, s, k_or_d, M, restart):
     """Algorithmic HBM bytes of each kernel of one call (list, launch order)."""
-    if method in ("extrap", "last"):
+    if method in ("extrap", "last", "spextrap"):
         if call == "form":
             return [N * (k_or_d * s + 8)] if k_or_d > 0 else []
         return [N * (8 + s)]
@@ -52,7 +57,10 @@ def kernel_bytes(method, call, N, s, k_or_d, M, restart):
         return [N * (d * s + 8) if d > 0 else 0, 0, N * (d * s + 8)]
     if restart:
         return [N * (8 + 2 * s), 0, 0, 0, 0, 0]
-    return [N * (16 + d * s), 0, N * (2 * d * s + 8), 0, N * (2 * d * s + 16 + 2 * s), 0]
+    reorth = N * ((1 if method.endswith("_l2") else 2) * d * s + 8)
+    if method.startswith("projqr") and d == M:      # rolling drop: every column rotated in place
+        return [N * (16 + d * s), 0, reorth, 0, N * (4 * d * s + 16), 0]
+    return [N * (16 + d * s), 0, reorth, 0, N * (2 * d * s + 16 + 2 * s), 0]
 
 
 def parse():
@@ -223,15 +231,16 @@ def main():
         s = L.ELEM_BYTES[L.DTYPES[dtype]]
         ctx, xs, sh, x64 = {}, {}, {}, None
         for m in methods:
-            ctx[m] = L.guess_create_ex(N, 1 if m == "last" else M, L.METHODS[m],
-                                       args.degree if m == "extrap" else 0, L.DTYPES[dtype], 1e-6,
-                                       op.handle, L.stream_handle())
+            meth, inner = L.parse_method(m)
+            ctx[m] = L.guess_create_ex(N, 1 if m == "last" else M, meth,
+                                       args.degree if m in ("extrap", "spextrap") else 0, L.DTYPES[dtype], 1e-6,
+                                       op.handle, L.stream_handle(), inner)
             L.guess_profile(ctx[m], True)
             xs[m] = torch.zeros(N, dtype=torch.float64, device="cuda")
             if shadow:
-                sh[m] = L.guess_create_ex(N, 1 if m == "last" else M, L.METHODS[m],
-                                          args.degree if m == "extrap" else 0, L.F64, 1e-6, op.handle,
-                                          L.stream_handle())
+                sh[m] = L.guess_create_ex(N, 1 if m == "last" else M, meth,
+                                          args.degree if m in ("extrap", "spextrap") else 0, L.F64, 1e-6, op.handle,
+                                          L.stream_handle(), inner)
         if shadow:
             x64 = torch.empty(N, dtype=torch.float64, device="cuda")
         stats = {m: {"iters": [], "guess_ms": 0.0, "guess_bytes": 0.0, "solve_ms": 0.0, "relres": [],
@@ -245,7 +254,10 @@ def main():
                 g, x = ctx[m], xs[m]
                 inf0 = L.guess_get_info(g)
                 kd = inf0["count"]
-                kd_form = min(kd, M) if m != "proj" else kd
+                if m == "spextrap":
+                    kd_form = min(args.degree, kd - 1) + 1 if kd > 0 else 0    # slots read
+                else:
+                    kd_form = kd if m.startswith("proj") else min(kd, M)
                 L.guess_form(g, b, x)
                 tf = L.guess_kernel_times(g)
                 if shadow and timed:
@@ -269,7 +281,11 @@ def main():
                 S["iters"].append(it)
                 S["relres"].append(rr)
                 S["solve_ms"] += ev[0].elapsed_time(ev[1])
-                restart = m == "proj" and (inf1["count"] == 0 or inf1["count"] >= M)
+                dd = inf1["count"]
+                if m.startswith("projqr"):
+                    restart = dd == 0 or M == 1
+                else:
+                    restart = m.startswith("proj") and (dd == 0 or dd >= M)
                 for call, times, kdd in (("form", tf, kd_form), ("update", tu, inf1["count"])):
                     names = KERNELS[(m, call)]
                     byts = kernel_bytes(m, call, N, s, kdd, M, restart)
@@ -280,7 +296,8 @@ def main():
                         S["guess_bytes"] += by
                         if by == 0:
                             continue
-                        ks = kstat.setdefault(name, [0, 0.0, 0.0])
+                        key = name if m in ("extrap", "proj") else f"{name}:{m}"
+                        ks = kstat.setdefault(key, [0, 0.0, 0.0])
                         ks[0] += 1
                         ks[1] += ms
                         ks[2] += by

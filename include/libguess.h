@@ -3,15 +3,19 @@
  *
  * Method: A. P. Austin, N. Chalmers, T. Warburton, "Initial Guesses for
  * Sequences of Linear Systems in a GPU-Accelerated Incompressible Flow
- * Solver" (2020).  Two guess methods are provided:
+ * Solver" (2020).  The guess methods are:
  *
  *   - stabilized least-squares polynomial extrapolation (§3.2, eq.
  *     LSQRCoeffs; the guess is the fixed combination of eq. ExtrapExpn),
  *     with the previous-solution guess as its M = 1 case (§3.1);
- *   - Fischer's projection, classic restart variant (§2, Algorithm 1), in
- *     A-orthonormal form: the history keeps X with X^T A X = I and B = A X,
- *     the guess is X (X^T b), and each update applies A once and runs
- *     twice-iterated classical Gram-Schmidt in the A inner product.
+ *   - sparse extrapolation (§3.3, eq. CPQRCoeffs): m+1 of the M stored
+ *     solutions, chosen by column-pivoted QR;
+ *   - Fischer's projection (§2), with the history bounded by restarts
+ *     (classic, Algorithm 1) or by a rolling window kept with a QR update
+ *     (Algorithm 2).  By default in A-orthonormal form: the history keeps X
+ *     with X^T A X = I and B = A X and the guess is X (X^T b); optionally in
+ *     the paper's l2 form: B^T B = I and the guess is X (B^T b).  Each update
+ *     applies A once and runs twice-iterated classical Gram-Schmidt.
  *
  * around a matrix-free 7-point Helmholtz / variable-coefficient operator
  * and a Jacobi-preconditioned CG (§5.3) that judges the guesses.
@@ -50,7 +54,16 @@ enum {
     GUESS_ZERO = 0,   /* x0 = 0                                                    */
     GUESS_LAST = 1,   /* x0 = previous solution (extrapolation with M = 1, §3.1)    */
     GUESS_EXTRAP = 2, /* least-squares extrapolation of degree m over M solutions  */
-    GUESS_PROJ = 3    /* A-orthonormal projection, classic restart (§2, Alg. 1)     */
+    GUESS_PROJ = 3,   /* A-orthonormal projection, classic restart (§2, Alg. 1)     */
+    GUESS_SPEXTRAP = 4, /* sparse extrapolation: m+1 of M solutions chosen by
+                           column-pivoted QR (§3.3, eq. CPQRCoeffs)               */
+    GUESS_PROJ_QR = 5   /* projection, rolling window with QR update (§2, Alg. 2) */
+};
+
+/* projection inner product */
+enum {
+    GUESS_INNER_A = 0,  /* X^T A X = I, x0 = X (X^T b): minimises the A-norm error       */
+    GUESS_INNER_L2 = 1  /* B^T B = I, x0 = X (B^T b): minimises ||b - A x0||_2 (§2)      */
 };
 
 /* storage format of the history vectors */
@@ -118,12 +131,13 @@ int pcg_solve_ex(guess_op_t A, const double *b, double *x, double rtol, int maxi
 typedef struct guess_opts {
     int64_t N;          /* vector length, >= 1                                      */
     int M;              /* history size, 1 <= M <= GUESS_MAX_M                      */
-    int method;         /* GUESS_ZERO / LAST / EXTRAP / PROJ                         */
-    int degree;         /* EXTRAP: polynomial degree m, 0 <= m <= M - 1              */
+    int method;         /* GUESS_ZERO / LAST / EXTRAP / PROJ / SPEXTRAP / PROJ_QR    */
+    int degree;         /* EXTRAP, SPEXTRAP: polynomial degree m, 0 <= m <= M - 1    */
     int dtype;          /* storage format of the history (GUESS_F64 ...)             */
     double eps_rel;     /* PROJ: reject if nu <= eps_rel * nu0; <= 0 selects 1e-6    */
     guess_op_t op;      /* PROJ: operator applied in guess_update when Ax == NULL    */
     void *stream;       /* hipStream_t; NULL = null stream                           */
+    int inner;          /* PROJ, PROJ_QR: GUESS_INNER_A (default) or GUESS_INNER_L2  */
 } guess_opts;
 
 #define GUESS_MAX_M 16
@@ -146,8 +160,10 @@ size_t guess_workspace_bytes(int64_t N, int M, int method, int dtype);
  *     first (eq. ExtrapExpn), with beta the least-squares weights of degree
  *     min(m, k-1) over k nodes (warm-up while k < M); x0 = 0 when k = 0.
  *     b is not read and may be NULL.  x0 may alias the caller's solve buffer.
- *   PROJ: x0 = X (X^T b), x0 = 0 when the history is empty.  b is required
- *     and must not alias x0.
+ *   SPEXTRAP: as EXTRAP with the sparse weights of guess_spextrap_weights;
+ *     only the m+1 solutions with a nonzero weight are read.
+ *   PROJ, PROJ_QR: x0 = X (X^T b) (l2: X (B^T b)), x0 = 0 when the
+ *     history is empty.  b is required and must not alias x0.
  *   ZERO: x0 = 0.
  * FP64 history accumulates in FP64; reduced-precision history is read,
  * widened and accumulated in FP32 (extrapolation) or FP64 (projection).
@@ -165,6 +181,15 @@ int guess_form(guess_t g, const double *b, double *x0);
  *     then the new pair is kept iff nu > eps_rel * nu0 (nu, nu0 the A-norms
  *     after / before orthogonalisation).  The decision is taken on the
  *     device; a non-finite nu rejects the vector and sets a sticky flag.
+ *   PROJ_QR: as PROJ, except that a full history (d = M) drops its oldest
+ *     solution instead of restarting: the factor R of raw solutions = X R
+ *     loses its first column and Givens rotations of neighbouring rows make
+ *     it triangular again (rotation of a over b: c = |a|/r, s = sign(a) b/r,
+ *     r = sqrt(a^2 + b^2), sign(0) = 1); the columns of X and B are rotated
+ *     alike, then the new solution is orthogonalised as above.  With M = 1
+ *     every update replaces the single column.
+ *   GUESS_INNER_L2: inner products b_j^T b~ and norms ||b~||_2 in place of
+ *     the A inner product and A-norm.
  *   ZERO: nothing.
  */
 int guess_update(guess_t g, const double *x, const double *Ax);
@@ -181,6 +206,8 @@ typedef struct guess_info {
     double nu, nu0;     /* PROJ: last A-norms after / before Gram-Schmidt             */
     double form_bytes;  /* algorithmic HBM bytes of the last guess_form                */
     double update_bytes;/* algorithmic HBM bytes of the last guess_update              */
+    int drops;          /* PROJ_QR: oldest-solution drops so far                       */
+    int inner;          /* PROJ, PROJ_QR: GUESS_INNER_A / GUESS_INNER_L2               */
 } guess_info;
 
 /* Snapshot of the context state.  Synchronises the context's stream. */
@@ -196,10 +223,31 @@ int guess_reset(guess_t g);
  */
 int guess_extrap_weights(int m, int k, double *beta);
 
+/*
+ * Sparse extrapolation weights (§3.3, eq. CPQRCoeffs): column-pivoted QR of
+ * V^T (Legendre basis on the nodes of §3.2) selects m+1 of the k stored
+ * solutions; their weights make the scheme exact for polynomials of degree
+ * <= m (eq. PolyExactness) and the other k-m-1 weights are exactly 0.
+ * Pivot norms within a relative 1e-10 of the largest count as tied and the
+ * oldest tied solution is taken.  Host-only, FP64; beta[0] multiplies the
+ * oldest solution.  Requires 1 <= k <= GUESS_MAX_M, 0 <= m <= k - 1.
+ */
+int guess_spextrap_weights(int m, int k, double *beta);
+
 /* Copy stored history vector j (PROJ: column j of X (which = 0) or B
  * (which = 1), scale applied; EXTRAP: j-th oldest stored solution) into
  * the FP64 device vector out.  For tests and checkpoints; synchronises. */
 int guess_history_get(guess_t g, int which, int j, double *out);
+
+/*
+ * PROJ, PROJ_QR: the triangular factor of the history, raw solutions = X R
+ * (§2, Algorithm 2; kept for both variants), with X the true columns.  The
+ * raw solutions are the accepted ones since the last restart (classic) or
+ * the window of the last d accepted ones (rolling).  Writes *d and the d x d
+ * factor row-major into R (room for GUESS_MAX_M^2 values, host memory).
+ * Synchronises the context's stream.
+ */
+int guess_proj_factor(guess_t g, double *R, int *d);
 
 /*
  * Per-kernel timing (tracing aid).  With profiling enabled every kernel that

@@ -18,11 +18,16 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "_lib", "libguess.so")
-SOURCES = ["proj_f64.hip", "proj_f32.hip", "proj_f16.hip", "proj_bf16.hip", "pcg.hip", "extrap.hip",
-           "proj.hip", "op.hip", "vec.hip", "host.hip"]
-# per-source extra flags: PCG's stencil kernel issues ~30 loads per chunk;
-# the max-ILP scheduler groups them (measured faster there, slower elsewhere)
-EXTRA_FLAGS = {"pcg.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp", "-DLG_WAVES_MIN=2"]}
+# (source, object name, extra flags).  PCG's stencil kernel issues ~30 loads
+# per chunk; the max-ILP scheduler groups them (measured faster there, slower
+# elsewhere).  The projection kernels are compiled once per storage format
+# and variant (bit 1: rolling QR, bit 2: l2 inner product).
+_DTYPES = ["GUESS_F64", "GUESS_F32", "GUESS_F16", "GUESS_BF16"]
+UNITS = [("proj_inst.hip", f"proj_{dt[6:].lower()}_v{vf}", [f"-DLG_PROJ_DT={dt}", f"-DLG_PROJ_VF={vf}"])
+         for dt in _DTYPES for vf in range(4)]
+UNITS += [("pcg.hip", "pcg", ["-mllvm", "-amdgpu-sched-strategy=max-ilp", "-DLG_WAVES_MIN=2"])]
+UNITS += [(src, src[:-4], []) for src in ("extrap.hip", "proj.hip", "op.hip", "vec.hip", "host.hip")]
+SOURCES = sorted({u[0] for u in UNITS})
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -49,9 +54,10 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *HIPCC_FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit) -> str:
+    src, name, extra = unit
+    obj = os.path.join(OBJDIR, name + ".o")
+    cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -61,9 +67,9 @@ def _compile(src: str) -> str:
 def build(jobs: int = None) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     os.makedirs(os.path.dirname(LIB), exist_ok=True)
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    jobs = jobs or min(len(UNITS), os.cpu_count() or 1)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(_compile, UNITS))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <numeric>
 #include <new>
 #include <string>
 #include <vector>
@@ -321,10 +322,83 @@ extern "C" int guess_extrap_weights(int m, int k, double *beta) {
     return GUESS_OK;
 }
 
+// Sparse extrapolation weights (§3.3, eq. CPQRCoeffs).  Column-pivoted QR
+// of V^T (Legendre basis, nodes as above) picks m+1 history nodes: each
+// pivot is the node whose column has the largest component orthogonal to
+// the nodes already taken (modified Gram-Schmidt here).  Norms within a
+// relative 1e-10 of the maximum count as equal and the oldest such node
+// wins: the first-maximum rule, made insensitive to the rounding that
+// separates the exact ties the symmetric nodes produce.  Given the nodes S,
+// the weights solve (V_S)^T beta_S = v, i.e. they are the Lagrange weights
+// of the interpolant through S evaluated at the new node.
+extern "C" int guess_spextrap_weights(int m, int k, double *beta) {
+    if (!beta) return fail(GUESS_EINVAL, "guess_spextrap_weights: beta is NULL");
+    if (k < 1 || k > GUESS_MAX_M || m < 0 || m > k - 1)
+        return fail(GUESS_EINVAL, "guess_spextrap_weights: need 1 <= k <= 16 and 0 <= m <= k-1");
+    for (int i = 0; i < k; ++i) beta[i] = 0.0;
+    if (k == 1) {
+        beta[0] = 1.0;
+        return GUESS_OK;
+    }
+    const int n = m + 1;
+    const double h = 2.0 / (k - 1);
+    double t[GUESS_MAX_M];
+    double C[GUESS_MAX_M][GUESS_MAX_M];  // C[i] = column i of V^T, then its residual
+    for (int i = 0; i < k; ++i) {
+        t[i] = -1.0 + i * h;
+        C[i][0] = 1.0;
+        if (n > 1) C[i][1] = t[i];
+        for (int j = 1; j + 1 < n; ++j) C[i][j + 1] = ((2 * j + 1) * t[i] * C[i][j] - j * C[i][j - 1]) / (j + 1);
+    }
+    bool taken[GUESS_MAX_M] = {};
+    int S[GUESS_MAX_M];
+    for (int p = 0; p < n; ++p) {
+        double nn[GUESS_MAX_M], mx = 0.0;
+        for (int i = 0; i < k; ++i) {
+            nn[i] = 0.0;
+            if (taken[i]) continue;
+            for (int j = 0; j < n; ++j) nn[i] += C[i][j] * C[i][j];
+            mx = nn[i] > mx ? nn[i] : mx;
+        }
+        if (!(mx > 0.0)) return fail(GUESS_EINVAL, "guess_spextrap_weights: rank-deficient basis");
+        int piv = -1;
+        for (int i = 0; i < k && piv < 0; ++i)
+            if (!taken[i] && nn[i] >= mx * (1.0 - 1e-10)) piv = i;
+        taken[piv] = true;
+        S[p] = piv;
+        double q[GUESS_MAX_M];
+        const double qn = std::sqrt(nn[piv]);
+        for (int j = 0; j < n; ++j) q[j] = C[piv][j] / qn;
+        for (int i = 0; i < k; ++i) {
+            if (taken[i]) continue;
+            double dot = 0.0;
+            for (int j = 0; j < n; ++j) dot += q[j] * C[i][j];
+            for (int j = 0; j < n; ++j) C[i][j] -= dot * q[j];
+        }
+    }
+    // In units of h the nodes are the integers 0..k-1 and the new node is k,
+    // so each weight is a ratio of integer products: exact in 64 bits
+    // (|numerator| <= 16^15), reduced, then one rounding to FP64.
+    for (int a = 0; a < n; ++a) {
+        int64_t num = 1, den = 1;
+        for (int b = 0; b < n; ++b) {
+            if (b == a) continue;
+            num *= (int64_t)(k - S[b]);
+            den *= (int64_t)(S[a] - S[b]);
+            const int64_t g = std::gcd(num < 0 ? -num : num, den < 0 ? -den : den);
+            num /= g;
+            den /= g;
+        }
+        beta[S[a]] = (double)num / (double)den;
+    }
+    return GUESS_OK;
+}
+
 // ====================================================================== context
 struct guess_ctx {
     int64_t N = 0, ld = 0;
     int M = 1, method = GUESS_ZERO, degree = 0, dtype = GUESS_F64, es = 8;
+    int inner = GUESS_INNER_A, vf = 0;   // projection: inner product, kernel variant flags
     double eps_rel = 1e-6;
     guess_op_t op = nullptr;
     hipStream_t stream = nullptr;
@@ -358,14 +432,21 @@ static void ctx_free(guess_ctx *g) {
     delete g;
 }
 
+static bool ring_method(int method) {
+    return method == GUESS_LAST || method == GUESS_EXTRAP || method == GUESS_SPEXTRAP;
+}
+static bool proj_method(int method) { return method == GUESS_PROJ || method == GUESS_PROJ_QR; }
+
 extern "C" size_t guess_workspace_bytes(int64_t N, int M, int method, int dtype) {
     const int es = esize(dtype);
     if (N < 1 || M < 1 || es == 0) return 0;
     const size_t col = (size_t)col_stride(N) * es;
     switch (method) {
         case GUESS_LAST: return col;
-        case GUESS_EXTRAP: return col * M;
+        case GUESS_EXTRAP:
+        case GUESS_SPEXTRAP: return col * M;
         case GUESS_PROJ:
+        case GUESS_PROJ_QR:
             return 2 * col * M + (size_t)N * 8 + sizeof(double) * lg::kMaxPartialBlocks * lg::kMaxDots +
                    sizeof(lg::ProjState);
     }
@@ -388,13 +469,15 @@ extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
     int M = o->M;
     if (o->method == GUESS_LAST) M = 1;
     if (o->N < 1) return fail(GUESS_EINVAL, "guess_create: need N >= 1");
-    if (o->method < GUESS_ZERO || o->method > GUESS_PROJ) return fail(GUESS_EINVAL, "guess_create: unknown method");
+    if (o->method < GUESS_ZERO || o->method > GUESS_PROJ_QR) return fail(GUESS_EINVAL, "guess_create: unknown method");
     if (o->method != GUESS_ZERO && (M < 1 || M > GUESS_MAX_M))
         return fail(GUESS_EINVAL, "guess_create: need 1 <= M <= 16");
     const int degree = o->method == GUESS_LAST ? 0 : o->degree;
-    if (o->method == GUESS_EXTRAP && (degree < 0 || degree > M - 1))
+    if ((o->method == GUESS_EXTRAP || o->method == GUESS_SPEXTRAP) && (degree < 0 || degree > M - 1))
         return fail(GUESS_EINVAL, "guess_create: need 0 <= degree <= M-1");
     if (esize(o->dtype) == 0) return fail(GUESS_EINVAL, "guess_create: unknown dtype");
+    if (o->inner != GUESS_INNER_A && o->inner != GUESS_INNER_L2)
+        return fail(GUESS_EINVAL, "guess_create: unknown inner product");
     if (o->op && o->op->g.n != o->N) return fail(GUESS_EINVAL, "guess_create: operator size differs from N");
     guess_ctx *g = new (std::nothrow) guess_ctx();
     if (!g) return fail(GUESS_ENOMEM, "guess_create: host allocation failed");
@@ -406,6 +489,8 @@ extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
     g->dtype = o->dtype;
     g->es = esize(o->dtype);
     g->eps_rel = o->eps_rel > 0.0 ? o->eps_rel : 1e-6;
+    g->inner = o->inner;
+    g->vf = (o->method == GUESS_PROJ_QR ? 1 : 0) | (o->inner == GUESS_INNER_L2 ? 2 : 0);
     g->op = o->op;
     g->stream = (hipStream_t)o->stream;
     const size_t col = (size_t)g->ld * g->es;
@@ -419,9 +504,9 @@ extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
         return GUESS_OK;
     };
     int rc = GUESS_OK;
-    if (g->method == GUESS_EXTRAP || g->method == GUESS_LAST) {
+    if (ring_method(g->method)) {
         rc = alloc(&g->ring, col * g->M);
-    } else if (g->method == GUESS_PROJ) {
+    } else if (proj_method(g->method)) {
         rc = alloc(&g->X, col * g->M);
         if (rc == GUESS_OK) rc = alloc(&g->B, col * g->M);
         if (rc == GUESS_OK) rc = alloc((void **)&g->w, (size_t)g->N * 8);
@@ -469,7 +554,8 @@ extern "C" int guess_set_op(guess_t g, guess_op_t A) {
 
 static int ring_weights(guess_ctx *g, int m, int k, const double **out) {
     if (!g->have_beta[k][m]) {
-        LG_TRY(guess_extrap_weights(m, k, g->beta[k][m]));
+        if (g->method == GUESS_SPEXTRAP) LG_TRY(guess_spextrap_weights(m, k, g->beta[k][m]));
+        else LG_TRY(guess_extrap_weights(m, k, g->beta[k][m]));
         g->have_beta[k][m] = true;
     }
     *out = g->beta[k][m];
@@ -487,6 +573,7 @@ static lg::ProjBufs proj_bufs(guess_ctx *g) {
     p.ld = g->ld;
     p.M = g->M;
     p.dtype = g->dtype;
+    p.vf = g->vf;
     return p;
 }
 
@@ -501,7 +588,8 @@ extern "C" int guess_form(guess_t g, const double *b, double *x0) {
             g->form_bytes = 8.0 * N;
             return check_launch("guess_form");
         case GUESS_LAST:
-        case GUESS_EXTRAP: {
+        case GUESS_EXTRAP:
+        case GUESS_SPEXTRAP: {
             const int k = g->count;
             if (k == 0) {
                 lg::launch_fill_zero(x0, N, g->stream);
@@ -511,15 +599,23 @@ extern "C" int guess_form(guess_t g, const double *b, double *x0) {
             const int m = g->degree < k - 1 ? g->degree : k - 1;
             const double *beta;
             LG_TRY(ring_weights(g, m, k, &beta));
+            // stored solutions with a nonzero weight, oldest first (all of them
+            // for least-squares weights, m+1 for the sparse scheme)
             const void *slots[GUESS_MAX_M];
+            double w[GUESS_MAX_M];
+            int nz = 0;
             const int oldest = ((g->head - k) % g->M + g->M) % g->M;
-            for (int j = 0; j < k; ++j)
-                slots[j] = (const char *)g->ring + (size_t)((oldest + j) % g->M) * g->ld * g->es;
-            LG_TRY(lg::launch_extrap_form(g->dtype, k, slots, beta, x0, N, g->stream, g->prof ? &g->kev : nullptr));
-            g->form_bytes = (double)N * (k * g->es + 8);
+            for (int j = 0; j < k; ++j) {
+                if (g->method == GUESS_SPEXTRAP && beta[j] == 0.0) continue;
+                slots[nz] = (const char *)g->ring + (size_t)((oldest + j) % g->M) * g->ld * g->es;
+                w[nz++] = beta[j];
+            }
+            LG_TRY(lg::launch_extrap_form(g->dtype, nz, slots, w, x0, N, g->stream, g->prof ? &g->kev : nullptr));
+            g->form_bytes = (double)N * (nz * g->es + 8);
             return check_launch("guess_form");
         }
-        case GUESS_PROJ: {
+        case GUESS_PROJ:
+        case GUESS_PROJ_QR: {
             if (!b) return fail(GUESS_EINVAL, "guess_form: projection needs b");
             if (b == x0) return fail(GUESS_EINVAL, "guess_form: b and x0 must not alias");
             if (!aligned16(b)) return fail(GUESS_EINVAL, "guess_form: b must be 16-byte aligned");
@@ -541,7 +637,8 @@ extern "C" int guess_update(guess_t g, const double *x, const double *Ax) {
             g->update_bytes = 0.0;
             return GUESS_OK;
         case GUESS_LAST:
-        case GUESS_EXTRAP: {
+        case GUESS_EXTRAP:
+        case GUESS_SPEXTRAP: {
             void *slot = (char *)g->ring + (size_t)g->head * g->ld * g->es;
             LG_TRY(lg::launch_ring_store(g->dtype, x, slot, N, g->stream, g->prof ? &g->kev : nullptr));
             g->head = (g->head + 1) % g->M;
@@ -549,7 +646,8 @@ extern "C" int guess_update(guess_t g, const double *x, const double *Ax) {
             g->update_bytes = (double)N * (8 + g->es);
             return check_launch("guess_update");
         }
-        case GUESS_PROJ: {
+        case GUESS_PROJ:
+        case GUESS_PROJ_QR: {
             if (!Ax && !g->op) return fail(GUESS_EINVAL, "guess_update: projection needs Ax or an operator");
             if (Ax == x) return fail(GUESS_EINVAL, "guess_update: Ax must not alias x");
             LG_TRY(lg::launch_proj_update(proj_bufs(g), g->op ? &g->op->g : nullptr, x, Ax, g->stream,
@@ -572,7 +670,8 @@ extern "C" int guess_get_info(guess_t g, guess_info *info) {
     info->degree = g->degree;
     info->form_bytes = g->form_bytes;
     info->update_bytes = g->update_bytes;
-    if (g->method == GUESS_PROJ) {
+    info->inner = g->inner;
+    if (proj_method(g->method)) {
         LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));
         LG_HIP(hipStreamSynchronize(g->stream));
         const lg::ProjState &s = *g->host_st;
@@ -583,12 +682,18 @@ extern "C" int guess_get_info(guess_t g, guess_info *info) {
         info->nonfinite = s.nonfinite;
         info->nu = s.nu;
         info->nu0 = s.nu0;
+        info->drops = s.drops;
         const double N = (double)g->N, es = g->es;
         if (g->form_bytes < 0) info->form_bytes = 2.0 * N * (s.form_d * es + 8.0) - (s.form_d == 0 ? N * 8.0 : 0.0);
         if (g->update_bytes < 0) {
+            // apply 16 + d s; reorth 2 d s + 8 (l2: d s + 8); write 2 d s + 16 + 2 s,
+            // or with a rolling drop 4 d s + 16; restart 8 (+8) + 2 s
             const int d = s.upd_d;
-            if (d == 0 || d >= g->M) info->update_bytes = N * (8.0 + 2.0 * es + (g->last_update_ax ? 8.0 : 0.0));
-            else info->update_bytes = N * (5.0 * d * es + 2.0 * es + 40.0);
+            const bool restart = d == 0 || (g->method == GUESS_PROJ_QR ? g->M == 1 : d >= g->M);
+            const double reorth = (g->inner == GUESS_INNER_L2 ? 1.0 : 2.0) * d * es + 8.0;
+            if (restart) info->update_bytes = N * (8.0 + 2.0 * es + (g->last_update_ax ? 8.0 : 0.0));
+            else if (s.drop) info->update_bytes = N * (16.0 + d * es + reorth + 4.0 * d * es + 16.0);
+            else info->update_bytes = N * (16.0 + d * es + reorth + 2.0 * d * es + 16.0 + 2.0 * es);
         }
     } else {
         LG_HIP(hipStreamSynchronize(g->stream));
@@ -602,12 +707,13 @@ extern "C" int guess_reset(guess_t g) {
     if (!g) return fail(GUESS_EINVAL, "guess_reset: NULL context");
     g->count = 0;
     g->head = 0;
-    if (g->method == GUESS_PROJ) {
+    if (proj_method(g->method)) {
         LG_HIP(hipStreamSynchronize(g->stream));
         LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));
         LG_HIP(hipStreamSynchronize(g->stream));
         g->host_st->d = 0;
         g->host_st->mode = 0;
+        g->host_st->drop = 0;
         LG_HIP(hipMemcpyAsync(g->st, g->host_st, sizeof(lg::ProjState), hipMemcpyHostToDevice, g->stream));
         LG_HIP(hipStreamSynchronize(g->stream));
     }
@@ -651,12 +757,12 @@ extern "C" int guess_kernel_times(guess_t g, double *ms, int max, int *n) {
 
 extern "C" int guess_history_get(guess_t g, int which, int j, double *out) {
     if (!g || !out) return fail(GUESS_EINVAL, "guess_history_get: NULL argument");
-    if (g->method == GUESS_EXTRAP || g->method == GUESS_LAST) {
+    if (ring_method(g->method)) {
         if (j < 0 || j >= g->count) return fail(GUESS_EINVAL, "guess_history_get: index out of range");
         const int oldest = ((g->head - g->count) % g->M + g->M) % g->M;
         const void *src = (const char *)g->ring + (size_t)((oldest + j) % g->M) * g->ld * g->es;
         LG_TRY(lg::launch_widen(g->dtype, src, 1.0, out, g->N, g->stream));
-    } else if (g->method == GUESS_PROJ) {
+    } else if (proj_method(g->method)) {
         LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));
         LG_HIP(hipStreamSynchronize(g->stream));
         if (j < 0 || j >= g->host_st->d || (which != 0 && which != 1))
@@ -669,6 +775,18 @@ extern "C" int guess_history_get(guess_t g, int which, int j, double *out) {
     }
     LG_TRY(check_launch("guess_history_get"));
     LG_HIP(hipStreamSynchronize(g->stream));
+    return GUESS_OK;
+}
+
+extern "C" int guess_proj_factor(guess_t g, double *R, int *d) {
+    if (!g || !R || !d) return fail(GUESS_EINVAL, "guess_proj_factor: NULL argument");
+    if (!proj_method(g->method)) return fail(GUESS_EINVAL, "guess_proj_factor: not a projection context");
+    LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));
+    LG_HIP(hipStreamSynchronize(g->stream));
+    const int n = g->host_st->d;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) R[i * n + j] = j >= i ? g->host_st->R[i][j] : 0.0;
+    *d = n;
     return GUESS_OK;
 }
 

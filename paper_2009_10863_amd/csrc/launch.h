@@ -41,13 +41,18 @@ struct ProjState {
     int M;
     int form_d;             // columns used by the last guess (written by proj_combine)
     int upd_d;              // columns at the start of the last update (written by proj_apply)
+    int drop;               // rolling variant: the current update drops the oldest column
+    int drops;              // rolling variant: drops so far
     int pad;
     double eps_rel;
     double nu0sq, nusq, nu0, nu;
     double scale[GUESS_MAX_M];   // column j of X (and B) = scale[j] * stored column j
     double gamma[GUESS_MAX_M];   // guess: x0 = sum_j gamma[j] * stored X_j
-    double c[GUESS_MAX_M];       // update: Gram-Schmidt coefficients (A inner product)
-    double cs[GUESS_MAX_M];      // update: c[j] * scale[j]
+    double c[GUESS_MAX_M];       // update: Gram-Schmidt coefficients (true units)
+    double cs[GUESS_MAX_M];      // update: coefficients of the stored columns
+    double R[GUESS_MAX_M][GUESS_MAX_M];  // raw solutions of the history = X R (upper triangular)
+    double gc[GUESS_MAX_M], gs[GUESS_MAX_M];  // rolling drop: Givens rotations (c, s)
+    double rot[GUESS_MAX_M][4];  // rolling drop: the rotations in stored units, per slot
 };
 
 // Device-resident state of a PCG solve (rho of iteration k in rho[k & 1]).
@@ -74,6 +79,7 @@ struct ProjBufs {
     ProjState *st;           // device state
     int64_t N, ld;           // ld: elements between consecutive columns
     int M, dtype;
+    int vf;                  // variant flags: 1 rolling QR, 2 l2 inner product
 };
 int launch_proj_form(const ProjBufs &p, const double *b, double *x0, hipStream_t s,
                      KEvents *ev = nullptr);

@@ -1,12 +1,29 @@
-// Kernels of Fischer's projection guess, classic restart variant (§2,
-// Algorithm 1), in A-orthonormal form: X^T A X = I, B = A X, guess
-// x0 = X (X^T b).
+// Kernels of Fischer's projection guess (§2).
+//
+// Two ways of bounding the history (template flag VF_QR):
+//   classic (Algorithm 1): when the history is full, restart from the new
+//     solution;
+//   rolling QR (Algorithm 2): when the history is full, drop the oldest
+//     solution: delete the first column of R (raw solutions = X R), return
+//     R to triangular form with Givens rotations of neighbouring rows and
+//     rotate the columns of X and B alongside, then add the new solution.
+// Two inner products (template flag VF_L2):
+//   A (default): X^T A X = I, B = A X, guess x0 = X (X^T b);
+//   l2 (the paper's own form): B^T B = I, guess x0 = X (B^T b).
 //
 // Columns are stored unnormalised with a per-column FP64 scale kept in the
 // device state (true column j = scale[j] * stored column j), so that the
 // normalisation of a new column, which needs its norm, does not cost an
-// extra pass over the data.  Every decision (restart, accept / reject) is
-// taken on the device.
+// extra pass over the data.  Every decision (restart, drop, accept / reject)
+// is taken on the device.
+//
+// The rolling drop costs no pass of its own.  The rotated basis is
+// X' = X W^T (first d-1 columns), W the product of the rotations, so inner
+// products with X' are W times inner products with X: the apply and reorth
+// kernels work on the old columns and the finishing kernels rotate the
+// small coefficient vectors.  The Gram-Schmidt write kernel then reads every
+// old column once, writes the rotated columns back in place and the new
+// orthogonalised pair into the last slot.
 //
 // Each reduction is split in two launches: a streaming kernel that writes
 // one row of partial sums per workgroup, and a one-workgroup finishing
@@ -15,21 +32,25 @@
 // device-wide cache write-back or invalidation is needed mid-kernel.
 //
 // Streaming kernels and algorithmic bytes per unknown (s = stored element
-// size, d the current number of columns):
-//   proj_dots      P_j = X_j^T b                      reads d s + 8
+// size, d the current number of columns, C = X for the A inner product and
+// C = B for l2):
+//   proj_dots      P_j = C_j^T b                      reads d s + 8
 //   proj_combine   x0 = sum_j gamma_j X_j             reads d s, writes 8
 //   proj_apply     w = A x (or the caller's A x),     reads 8 (+8), d s; writes 8
-//                  c1 = X^T w, nu0^2 = x^T w;
+//                  c1 = C^T w, nu0^2 = x^T w (w^T w);
 //                  restart: X_1 <- x, B_1 <- w        reads 8 (+8); writes 2 s
-//   proj_reorth    c2 = X^T (w - B c1)                reads 2 d s + 8
+//   proj_reorth    c2 = C^T (w - B c1)                reads 2 d s + 8 (l2: d s + 8)
 //   proj_gs_write  x'' = x - X c, w'' = w - B c,      reads 2 d s + 16; writes 2 s
-//                  nu^2 = x''^T w'', store in slot d
+//                  nu^2 = x''^T w'' (w''^T w''), store in slot d
+//                  rolling drop (d = M): also rotates  reads 2 M s + 16; writes 2 M s
 #pragma once
 
 #include "common.h"
 #include "launch.h"
 
 namespace lg {
+
+enum { VF_QR = 1, VF_L2 = 2 };
 
 struct ProjArgs {
     const void *X;
@@ -52,16 +73,31 @@ __device__ __forceinline__ void *colw(void *base, int64_t ld, int j) {
     return reinterpret_cast<typename Elem<DT>::T *>(base) + (int64_t)j * ld;
 }
 
-__device__ __forceinline__ bool proj_restart(const ProjState *st, int M) {
-    const int d = st->d;
-    return d == 0 || d >= M;
+// The update starts a new history: empty, or (classic) full.  With the
+// rolling variant and M = 1, dropping the only column and adding the new
+// one is the same as a restart.
+template <int VF>
+__device__ __forceinline__ bool proj_restart(int d, int M) {
+    if constexpr ((VF & VF_QR) != 0) return d == 0 || M == 1;
+    else return d == 0 || d >= M;
+}
+// largest number of columns the Gram-Schmidt kernels see
+template <int VF>
+constexpr int gs_max() {
+    return (VF & VF_QR) ? GUESS_MAX_M : GUESS_MAX_M - 1;
+}
+// the columns inner products are taken with
+template <int VF>
+__device__ __forceinline__ const void *dot_cols(const ProjArgs &a) {
+    return (VF & VF_L2) ? a.B : a.X;
 }
 
 // ------------------------------------------------------------------ form
-template <int DT>
+template <int DT, int VF>
 LG_REDUCE_KERNEL void proj_dots_kernel(ProjArgs a, const double *__restrict__ b) {
     __shared__ double lds[kLdsDoubles];
     const int d = a.st->d;
+    const void *C = dot_cols<VF>(a);
     const int64_t nc = nchunks(a.N), stride = (int64_t)gridDim.x * kBlock;
     dispatch_d<1, GUESS_MAX_M>(d, [&](auto Dc) {
         constexpr int D = decltype(Dc)::value;
@@ -72,7 +108,7 @@ LG_REDUCE_KERNEL void proj_dots_kernel(ProjArgs a, const double *__restrict__ b)
             const V4 bv = load4<GUESS_F64>(b, c);
             V4 xv[D];
 #pragma unroll
-            for (int j = 0; j < D; ++j) xv[j] = load4<DT>(colp<DT>(a.X, a.ld, j), c);
+            for (int j = 0; j < D; ++j) xv[j] = load4<DT>(colp<DT>(C, a.ld, j), c);
 #pragma unroll
             for (int j = 0; j < D; ++j)
 #pragma unroll
@@ -82,7 +118,7 @@ LG_REDUCE_KERNEL void proj_dots_kernel(ProjArgs a, const double *__restrict__ b)
             const int64_t i = tail_start(a.N) + threadIdx.x;
 #pragma unroll
             for (int j = 0; j < D; ++j)
-                acc[j] = __builtin_fma(load1<DT>(colp<DT>(a.X, a.ld, j), i), b[i], acc[j]);
+                acc[j] = __builtin_fma(load1<DT>(colp<DT>(C, a.ld, j), i), b[i], acc[j]);
         }
         block_partials<D>(acc, a.part, lds);
     });
@@ -123,10 +159,11 @@ __global__ __launch_bounds__(kBlock) void proj_combine_kernel(ProjArgs a, double
 }
 
 // ------------------------------------------------------------------ update
-template <int DT, bool VAR, bool HAVE_AX, bool AL>
+template <int DT, int VF, bool VAR, bool HAVE_AX, bool AL>
 LG_REDUCE_KERNEL void proj_apply_kernel(ProjArgs a, Grid g, const double *__restrict__ x,
                                         const double *__restrict__ Ax) {
     __shared__ double lds[kLdsDoubles];
+    constexpr bool L2 = (VF & VF_L2) != 0;
     const int d = a.st->d;
     const int64_t nc = nchunks(a.N);
     const ChunkRange cr = xcd_range(nc);
@@ -147,28 +184,29 @@ LG_REDUCE_KERNEL void proj_apply_kernel(ProjArgs a, Grid g, const double *__rest
         if constexpr (HAVE_AX) return Ax[i];
         else return apply_pt<VAR>(VecU{x}, g, i);
     };
-    if (d == 0 || d >= a.M) {
-        // restart: slot 1 <- x, B slot 1 <- A x; partial nu0^2 = x^T A x
+    if (proj_restart<VF>(d, a.M)) {
+        // restart: slot 1 <- x, B slot 1 <- A x; partial nu0^2 = x^T A x (l2: |A x|^2)
         double acc[1] = {0.0};
         for (int64_t c = cr.begin; c < cr.end; c += cr.step) {
             V4 xv;
             const V4 wv = xw4(c, xv);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(xv.v[e], wv.v[e], acc[0]);
+            for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[0]);
             store4<DT>(a.Xw, c, xv);
             store4<DT>(a.Bw, c, wv);
         }
         if (blockIdx.x == 0 && threadIdx.x < rem) {
             const int64_t i = tail_start(a.N) + threadIdx.x;
             const double wv = xw1(i);
-            acc[0] = __builtin_fma(x[i], wv, acc[0]);
+            acc[0] = __builtin_fma(L2 ? wv : x[i], wv, acc[0]);
             store1<DT>(a.Xw, i, x[i]);
             store1<DT>(a.Bw, i, wv);
         }
         block_partials<1>(acc, a.part, lds);
         return;
     }
-    dispatch_d<1, GUESS_MAX_M - 1>(d, [&](auto Dc) {
+    const void *C = dot_cols<VF>(a);
+    dispatch_d<1, gs_max<VF>()>(d, [&](auto Dc) {
         constexpr int D = decltype(Dc)::value;
         constexpr int ND = D + 1;
         double acc[ND];
@@ -177,12 +215,12 @@ LG_REDUCE_KERNEL void proj_apply_kernel(ProjArgs a, Grid g, const double *__rest
         for (int64_t c = cr.begin; c < cr.end; c += cr.step) {
             V4 xc[D];
 #pragma unroll
-            for (int j = 0; j < D; ++j) xc[j] = load4<DT>(colp<DT>(a.X, a.ld, j), c);
+            for (int j = 0; j < D; ++j) xc[j] = load4<DT>(colp<DT>(C, a.ld, j), c);
             V4 xv;
             const V4 wv = xw4(c, xv);
             if constexpr (!HAVE_AX) store4<GUESS_F64>(a.w, c, wv);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[D] = __builtin_fma(xv.v[e], wv.v[e], acc[D]);
+            for (int e = 0; e < 4; ++e) acc[D] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[D]);
 #pragma unroll
             for (int j = 0; j < D; ++j)
 #pragma unroll
@@ -192,21 +230,22 @@ LG_REDUCE_KERNEL void proj_apply_kernel(ProjArgs a, Grid g, const double *__rest
             const int64_t i = tail_start(a.N) + threadIdx.x;
             const double wv = xw1(i);
             if constexpr (!HAVE_AX) a.w[i] = wv;
-            acc[D] = __builtin_fma(x[i], wv, acc[D]);
+            acc[D] = __builtin_fma(L2 ? wv : x[i], wv, acc[D]);
 #pragma unroll
-            for (int j = 0; j < D; ++j) acc[j] = __builtin_fma(load1<DT>(colp<DT>(a.X, a.ld, j), i), wv, acc[j]);
+            for (int j = 0; j < D; ++j) acc[j] = __builtin_fma(load1<DT>(colp<DT>(C, a.ld, j), i), wv, acc[j]);
         }
         block_partials<ND>(acc, a.part, lds);
     });
 }
 
-template <int DT>
+template <int DT, int VF>
 LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ w) {
     __shared__ double lds[kLdsDoubles];
+    constexpr bool L2 = (VF & VF_L2) != 0;
     if (a.st->mode != 0) return;
     const int d = a.st->d;
     const int64_t nc = nchunks(a.N), stride = (int64_t)gridDim.x * kBlock;
-    dispatch_d<1, GUESS_MAX_M - 1>(d, [&](auto Dc) {
+    dispatch_d<1, gs_max<VF>()>(d, [&](auto Dc) {
         constexpr int D = decltype(Dc)::value;
         double cs[D], acc[D];
 #pragma unroll
@@ -215,11 +254,13 @@ LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ 
             acc[j] = 0.0;
         }
         for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
-            V4 bc[D], xc[D];
+            V4 bc[D], xc[L2 ? 1 : D];
 #pragma unroll
             for (int j = 0; j < D; ++j) bc[j] = load4<DT>(colp<DT>(a.B, a.ld, j), c);
+            if constexpr (!L2) {
 #pragma unroll
-            for (int j = 0; j < D; ++j) xc[j] = load4<DT>(colp<DT>(a.X, a.ld, j), c);
+                for (int j = 0; j < D; ++j) xc[j] = load4<DT>(colp<DT>(a.X, a.ld, j), c);
+            }
             V4 wv = load4<GUESS_F64>(w, c);
 #pragma unroll
             for (int j = 0; j < D; ++j)
@@ -228,7 +269,8 @@ LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ 
 #pragma unroll
             for (int j = 0; j < D; ++j)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) acc[j] = __builtin_fma(xc[j].v[e], wv.v[e], acc[j]);
+                for (int e = 0; e < 4; ++e)
+                    acc[j] = __builtin_fma(L2 ? bc[j].v[e] : xc[L2 ? 0 : j].v[e], wv.v[e], acc[j]);
         }
         if (blockIdx.x == 0 && threadIdx.x < tail_count(a.N)) {
             const int64_t i = tail_start(a.N) + threadIdx.x;
@@ -236,19 +278,99 @@ LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ 
 #pragma unroll
             for (int j = 0; j < D; ++j) wv = __builtin_fma(-cs[j], load1<DT>(colp<DT>(a.B, a.ld, j), i), wv);
 #pragma unroll
-            for (int j = 0; j < D; ++j) acc[j] = __builtin_fma(load1<DT>(colp<DT>(a.X, a.ld, j), i), wv, acc[j]);
+            for (int j = 0; j < D; ++j)
+                acc[j] = __builtin_fma(load1<DT>(colp<DT>(L2 ? a.B : a.X, a.ld, j), i), wv, acc[j]);
         }
         block_partials<D>(acc, a.part, lds);
     });
 }
 
-template <int DT>
+// Rolling drop, one array (X or B) of one chunk: subtract the projection
+// from v, rotate the D old columns in place (slot i <- rotated column i,
+// i < D-1) and store v in slot D-1.  rot[i] = {a, b, e, f} in stored units:
+// new_i = a t_i + b S_{i+1}, t_{i+1} = e t_i + f S_{i+1}, t_0 = S_0.
+template <int DT, int D>
+__device__ __forceinline__ void rotate_chunk(const void *S, void *Sw, int64_t ld, int64_t c, const double (&cs)[D],
+                                             const double (&rot)[D - 1][4], V4 &v) {
+    V4 col[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) col[j] = load4<DT>(colp<DT>(S, ld, j), c);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v.v[e] = __builtin_fma(-cs[j], col[j].v[e], v.v[e]);
+    V4 t = col[0];
+#pragma unroll
+    for (int i = 0; i < D - 1; ++i) {
+        V4 nw;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            nw.v[e] = __builtin_fma(rot[i][1], col[i + 1].v[e], rot[i][0] * t.v[e]);
+            t.v[e] = __builtin_fma(rot[i][3], col[i + 1].v[e], rot[i][2] * t.v[e]);
+        }
+        store4<DT>(colw<DT>(Sw, ld, i), c, nw);
+    }
+    store4<DT>(colw<DT>(Sw, ld, D - 1), c, v);
+}
+
+template <int DT, int D>
+__device__ __forceinline__ double rotate_one(const void *S, void *Sw, int64_t ld, int64_t i, const double (&cs)[D],
+                                             const double (&rot)[D - 1][4], double v) {
+    double col[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) col[j] = load1<DT>(colp<DT>(S, ld, j), i);
+#pragma unroll
+    for (int j = 0; j < D; ++j) v = __builtin_fma(-cs[j], col[j], v);
+    double t = col[0];
+#pragma unroll
+    for (int q = 0; q < D - 1; ++q) {
+        const double nw = __builtin_fma(rot[q][1], col[q + 1], rot[q][0] * t);
+        t = __builtin_fma(rot[q][3], col[q + 1], rot[q][2] * t);
+        store1<DT>(colw<DT>(Sw, ld, q), i, nw);
+    }
+    store1<DT>(colw<DT>(Sw, ld, D - 1), i, v);
+    return v;
+}
+
+template <int DT, int VF>
 LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict__ x,
                                            const double *__restrict__ w) {
     __shared__ double lds[kLdsDoubles];
+    constexpr bool L2 = (VF & VF_L2) != 0;
     if (a.st->mode != 0) return;
     const int d = a.st->d;
     const int64_t nc = nchunks(a.N), stride = (int64_t)gridDim.x * kBlock;
+    if constexpr ((VF & VF_QR) != 0) {
+        if (d == a.M) {
+            dispatch_d<2, GUESS_MAX_M>(d, [&](auto Dc) {
+                constexpr int D = decltype(Dc)::value;
+                double cs[D], rot[D - 1][4];
+#pragma unroll
+                for (int j = 0; j < D; ++j) cs[j] = a.st->cs[j];
+#pragma unroll
+                for (int i = 0; i < D - 1; ++i)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) rot[i][q] = a.st->rot[i][q];
+                double acc[1] = {0.0};
+                for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
+                    V4 xv = load4<GUESS_F64>(x, c);
+                    V4 wv = load4<GUESS_F64>(w, c);
+                    rotate_chunk<DT, D>(a.X, a.Xw, a.ld, c, cs, rot, xv);
+                    rotate_chunk<DT, D>(a.B, a.Bw, a.ld, c, cs, rot, wv);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[0]);
+                }
+                if (blockIdx.x == 0 && threadIdx.x < tail_count(a.N)) {
+                    const int64_t i = tail_start(a.N) + threadIdx.x;
+                    const double xv = rotate_one<DT, D>(a.X, a.Xw, a.ld, i, cs, rot, x[i]);
+                    const double wv = rotate_one<DT, D>(a.B, a.Bw, a.ld, i, cs, rot, w[i]);
+                    acc[0] = __builtin_fma(L2 ? wv : xv, wv, acc[0]);
+                }
+                block_partials<1>(acc, a.part, lds);
+            });
+            return;
+        }
+    }
     dispatch_d<1, GUESS_MAX_M - 1>(d, [&](auto Dc) {
         constexpr int D = decltype(Dc)::value;
         double cs[D];
@@ -273,7 +395,7 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
                     wv.v[e] = __builtin_fma(-cs[j], bc[j].v[e], wv.v[e]);
                 }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(xv.v[e], wv.v[e], acc[0]);
+            for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[0]);
             store4<DT>(Xd, c, xv);
             store4<DT>(Bd, c, wv);
         }
@@ -285,7 +407,7 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
                 xv = __builtin_fma(-cs[j], load1<DT>(colp<DT>(a.X, a.ld, j), i), xv);
                 wv = __builtin_fma(-cs[j], load1<DT>(colp<DT>(a.B, a.ld, j), i), wv);
             }
-            acc[0] = __builtin_fma(xv, wv, acc[0]);
+            acc[0] = __builtin_fma(L2 ? wv : xv, wv, acc[0]);
             store1<DT>(Xd, i, xv);
             store1<DT>(Bd, i, wv);
         }
@@ -298,7 +420,80 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
 // and take the step's decisions.
 enum { FIN_DOTS = 0, FIN_APPLY = 1, FIN_REORTH = 2, FIN_GS = 3 };
 
-template <int KIND>
+// Coefficients in the rotated basis from inner products p with the old
+// columns (true units): q = W p, keep q[0 .. D-2] (the last row of the
+// rotated factor is dropped).
+template <int D>
+__device__ __forceinline__ void rot_forward(const double *gc, const double *gs, double (&q)[D]) {
+#pragma unroll
+    for (int i = 0; i < D - 1; ++i) {
+        const double q0 = q[i], q1 = q[i + 1];
+        q[i] = gc[i] * q0 + gs[i] * q1;
+        q[i + 1] = -gs[i] * q0 + gc[i] * q1;
+    }
+}
+// Old-basis coefficients of X' y: W^T [y; 0].
+template <int D>
+__device__ __forceinline__ void rot_backward(const double *gc, const double *gs, double (&y)[D]) {
+    y[D - 1] = 0.0;
+#pragma unroll
+    for (int i = D - 2; i >= 0; --i) {
+        const double y0 = y[i], y1 = y[i + 1];
+        y[i] = gc[i] * y0 - gs[i] * y1;
+        y[i + 1] = gs[i] * y0 + gc[i] * y1;
+    }
+}
+
+// Rolling drop, first half (all threads of the workgroup take part): the
+// Givens rotations that return R(:, 2:M) to triangular form, the rotated
+// factor (written back to st->R, last row and column cleared), and the
+// per-slot rotation coefficients in stored units for proj_gs_write.
+__device__ __forceinline__ void qr_drop_plan(ProjState *st, int M) {
+    __shared__ double H[GUESS_MAX_M][GUESS_MAX_M + 1];
+    __shared__ double gcl[GUESS_MAX_M], gsl[GUESS_MAX_M];
+    const int t = threadIdx.x;
+    if (t < M * (M - 1)) {
+        const int i = t / (M - 1), j = t % (M - 1);
+        H[i][j] = st->R[i][j + 1];
+    }
+    __syncthreads();
+    for (int i = 0; i < M - 1; ++i) {
+        if (t == 0) {
+            const double a = H[i][i], b = H[i + 1][i];
+            const double r = hypot(a, b);
+            const double sg = a >= 0.0 ? 1.0 : -1.0;
+            const double c = fabs(a) / r, s = sg * b / r;
+            gcl[i] = c;
+            gsl[i] = s;
+            st->gc[i] = c;
+            st->gs[i] = s;
+            H[i][i] = sg * r;
+            H[i + 1][i] = 0.0;
+        }
+        __syncthreads();
+        if (t > i && t < M - 1) {
+            const double c = gcl[i], s = gsl[i];
+            const double h0 = H[i][t], h1 = H[i + 1][t];
+            H[i][t] = c * h0 + s * h1;
+            H[i + 1][t] = -s * h0 + c * h1;
+        }
+        __syncthreads();
+    }
+    if (t < M * M) {
+        const int i = t / M, j = t % M;
+        st->R[i][j] = (i < M - 1 && j < M - 1 && j >= i) ? H[i][j] : 0.0;
+    }
+    if (t < M - 1) {
+        const double c = gcl[t], s = gsl[t];
+        const double si = st->scale[t], sn = st->scale[t + 1];
+        st->rot[t][0] = c;
+        st->rot[t][1] = s * (sn / si);
+        st->rot[t][2] = -s * (si / sn);
+        st->rot[t][3] = c;
+    }
+}
+
+template <int KIND, int VF>
 __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
     __shared__ double lds[kLdsDoubles];
     ProjState *st = a.st;
@@ -311,12 +506,12 @@ __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
             final_sums<D>(a.part, nb, tot, lds);
             if (threadIdx.x < D) {
                 const double sc = st->scale[threadIdx.x];
-                // alpha_j = sc (X_j^T b); x0 = sum_j alpha_j sc X_j
+                // alpha_j = sc (C_j^T b); x0 = sum_j alpha_j sc X_j
                 st->gamma[threadIdx.x] = sc * (sc * tot[threadIdx.x]);
             }
         });
     } else if constexpr (KIND == FIN_APPLY) {
-        if (d == 0 || d >= a.M) {
+        if (proj_restart<VF>(d, a.M)) {
             double tot[1];
             final_sums<1>(a.part, nb, tot, lds);
             if (threadIdx.x == 0) {
@@ -327,21 +522,40 @@ __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
                 st->nu0 = nu0;
                 st->nu = nu0;
                 st->mode = 1;
-                st->restarts += 1;
+                st->drop = 0;
+                if ((VF & VF_QR) != 0 && d > 0) st->drops += 1;
+                else st->restarts += 1;
                 st->last_accepted = ok ? 1 : 0;
                 if (!isfinite(nu0)) st->nonfinite = 1;
                 st->scale[0] = ok ? 1.0 / nu0 : 0.0;
+                st->R[0][0] = ok ? nu0 : 0.0;
                 st->d = ok ? 1 : 0;
             }
             return;
         }
-        dispatch_d<1, GUESS_MAX_M - 1>(d, [&](auto Dc) {
+        const bool drop = (VF & VF_QR) != 0 && d == a.M;
+        if (drop) qr_drop_plan(st, a.M);
+        dispatch_d<1, gs_max<VF>()>(d, [&](auto Dc) {
             constexpr int D = decltype(Dc)::value;
             double tot[D + 1];
             final_sums<D + 1>(a.part, nb, tot, lds);
-            if (threadIdx.x < D) {
+            if (drop) {
+                if constexpr (D >= 2) {
+                    if (threadIdx.x == 0) {
+                        double q[D];
+#pragma unroll
+                        for (int j = 0; j < D; ++j) q[j] = st->scale[j] * tot[j];
+                        rot_forward<D>(st->gc, st->gs, q);
+#pragma unroll
+                        for (int j = 0; j < D - 1; ++j) st->c[j] = q[j];
+                        rot_backward<D>(st->gc, st->gs, q);
+#pragma unroll
+                        for (int j = 0; j < D; ++j) st->cs[j] = q[j] * st->scale[j];
+                    }
+                }
+            } else if (threadIdx.x < D) {
                 const double sc = st->scale[threadIdx.x];
-                const double cj = sc * tot[threadIdx.x];        // <X_j, A x>, X_j of unit A-norm
+                const double cj = sc * tot[threadIdx.x];        // <column j, x>, column of unit norm
                 st->c[threadIdx.x] = cj;
                 st->cs[threadIdx.x] = cj * sc;
             }
@@ -350,15 +564,34 @@ __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
                 st->nu0sq = tot[D];
                 st->nu0 = sqrt(tot[D]);
                 st->mode = 0;
+                st->drop = drop ? 1 : 0;
+                if (drop) st->drops += 1;
             }
         });
     } else if constexpr (KIND == FIN_REORTH) {
         if (st->mode != 0) return;
-        dispatch_d<1, GUESS_MAX_M - 1>(d, [&](auto Dc) {
+        const bool drop = (VF & VF_QR) != 0 && st->drop != 0;
+        dispatch_d<1, gs_max<VF>()>(d, [&](auto Dc) {
             constexpr int D = decltype(Dc)::value;
             double tot[D];
             final_sums<D>(a.part, nb, tot, lds);
-            if (threadIdx.x < D) {
+            if (drop) {
+                if constexpr (D >= 2) {
+                    if (threadIdx.x == 0) {
+                        double q[D];
+#pragma unroll
+                        for (int j = 0; j < D; ++j) q[j] = st->scale[j] * tot[j];
+                        rot_forward<D>(st->gc, st->gs, q);
+#pragma unroll
+                        for (int j = 0; j < D - 1; ++j) q[j] += st->c[j];
+#pragma unroll
+                        for (int j = 0; j < D - 1; ++j) st->c[j] = q[j];
+                        rot_backward<D>(st->gc, st->gs, q);
+#pragma unroll
+                        for (int j = 0; j < D; ++j) st->cs[j] = q[j] * st->scale[j];
+                    }
+                }
+            } else if (threadIdx.x < D) {
                 const double sc = st->scale[threadIdx.x];
                 const double cj = st->c[threadIdx.x] + sc * tot[threadIdx.x];
                 st->c[threadIdx.x] = cj;
@@ -366,22 +599,29 @@ __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
             }
         });
     } else {
-        if (st->mode != 0 || d < 1 || d >= a.M) return;
+        if (st->mode != 0 || d < 1 || d > a.M) return;
+        const bool drop = (VF & VF_QR) != 0 && st->drop != 0;
+        if (!drop && d >= a.M) return;
         double tot[1];
         final_sums<1>(a.part, nb, tot, lds);
+        const int slot = drop ? d - 1 : d;     // the new pair's column
+        const double nu = sqrt(tot[0]);        // NaN when rounding made it negative
+        const bool fin = isfinite(nu);
+        const bool ok = fin && nu > st->eps_rel * st->nu0;
+        // new column of the factor: raw x = X c + nu x~
+        if (ok && threadIdx.x < slot) st->R[threadIdx.x][slot] = st->c[threadIdx.x];
         if (threadIdx.x == 0) {
-            const double nu = sqrt(tot[0]);      // NaN when rounding made it negative
-            const bool fin = isfinite(nu);
-            const bool ok = fin && nu > st->eps_rel * st->nu0;
             st->nusq = tot[0];
             st->nu = nu;
             st->last_accepted = ok ? 1 : 0;
             if (!fin) st->nonfinite = 1;
             if (ok) {
-                st->scale[d] = 1.0 / nu;
-                st->d = d + 1;
+                st->scale[slot] = 1.0 / nu;
+                st->R[slot][slot] = nu;
+                st->d = slot + 1;
             } else {
                 st->rejects += 1;
+                st->d = slot;
             }
         }
     }
@@ -403,36 +643,36 @@ inline ProjArgs make_args(const ProjBufs &p) {
     return a;
 }
 
-template <int DT>
+template <int DT, int VF>
 void proj_form_dt(const ProjBufs &p, const double *b, double *x0, hipStream_t s, KEvents *ev) {
     const ProjArgs a = make_args(p);
     const int gr = stream_grid(nchunks(a.N), reduce_blocks());
-    klaunch(ev, 0, proj_dots_kernel<DT>, gr, kBlock, s, a, b);
-    klaunch(ev, 1, proj_fin_kernel<FIN_DOTS>, 1, kBlock, s, a, gr);
+    klaunch(ev, 0, proj_dots_kernel<DT, VF>, gr, kBlock, s, a, b);
+    klaunch(ev, 1, proj_fin_kernel<FIN_DOTS, VF>, 1, kBlock, s, a, gr);
     klaunch(ev, 2, proj_combine_kernel<DT>, stream_grid(nchunks(a.N), grid_cap()), kBlock, s, a, x0);
 }
 
-template <int DT>
+template <int DT, int VF>
 void proj_update_dt(const ProjBufs &p, const Grid *g, const double *x, const double *Ax, hipStream_t s,
                     KEvents *ev) {
     const ProjArgs a = make_args(p);
     const int gr = stream_grid(nchunks(a.N), reduce_blocks());
     const Grid gg = g ? *g : Grid{};
     if (Ax) {
-        klaunch(ev, 0, proj_apply_kernel<DT, false, true, true>, gr, kBlock, s, a, gg, x, Ax);
+        klaunch(ev, 0, proj_apply_kernel<DT, VF, false, true, true>, gr, kBlock, s, a, gg, x, Ax);
     } else if (g->kx) {
-        if (g->aligned) klaunch(ev, 0, proj_apply_kernel<DT, true, false, true>, gr, kBlock, s, a, gg, x, Ax);
-        else klaunch(ev, 0, proj_apply_kernel<DT, true, false, false>, gr, kBlock, s, a, gg, x, Ax);
+        if (g->aligned) klaunch(ev, 0, proj_apply_kernel<DT, VF, true, false, true>, gr, kBlock, s, a, gg, x, Ax);
+        else klaunch(ev, 0, proj_apply_kernel<DT, VF, true, false, false>, gr, kBlock, s, a, gg, x, Ax);
     } else {
-        if (g->aligned) klaunch(ev, 0, proj_apply_kernel<DT, false, false, true>, gr, kBlock, s, a, gg, x, Ax);
-        else klaunch(ev, 0, proj_apply_kernel<DT, false, false, false>, gr, kBlock, s, a, gg, x, Ax);
+        if (g->aligned) klaunch(ev, 0, proj_apply_kernel<DT, VF, false, false, true>, gr, kBlock, s, a, gg, x, Ax);
+        else klaunch(ev, 0, proj_apply_kernel<DT, VF, false, false, false>, gr, kBlock, s, a, gg, x, Ax);
     }
-    klaunch(ev, 1, proj_fin_kernel<FIN_APPLY>, 1, kBlock, s, a, gr);
+    klaunch(ev, 1, proj_fin_kernel<FIN_APPLY, VF>, 1, kBlock, s, a, gr);
     const double *w = Ax ? Ax : a.w;
-    klaunch(ev, 2, proj_reorth_kernel<DT>, gr, kBlock, s, a, w);
-    klaunch(ev, 3, proj_fin_kernel<FIN_REORTH>, 1, kBlock, s, a, gr);
-    klaunch(ev, 4, proj_gs_write_kernel<DT>, gr, kBlock, s, a, x, w);
-    klaunch(ev, 5, proj_fin_kernel<FIN_GS>, 1, kBlock, s, a, gr);
+    klaunch(ev, 2, proj_reorth_kernel<DT, VF>, gr, kBlock, s, a, w);
+    klaunch(ev, 3, proj_fin_kernel<FIN_REORTH, VF>, 1, kBlock, s, a, gr);
+    klaunch(ev, 4, proj_gs_write_kernel<DT, VF>, gr, kBlock, s, a, x, w);
+    klaunch(ev, 5, proj_fin_kernel<FIN_GS, VF>, 1, kBlock, s, a, gr);
 }
 
 }  // namespace lg

@@ -16,12 +16,23 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LIBGUESS_SO") or os.path.join(_HERE, "_lib", "libguess.so")
 
 # ---------------------------------------------------------------- constants
-ZERO, LAST, EXTRAP, PROJ = 0, 1, 2, 3
+ZERO, LAST, EXTRAP, PROJ, SPEXTRAP, PROJ_QR = 0, 1, 2, 3, 4, 5
+INNER_A, INNER_L2 = 0, 1
 F64, F32, F16, BF16 = 0, 1, 2, 3
 OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 STOP_RHS, STOP_INITRESID = 0, 1
 MAX_M = 16
-METHODS = {"zero": ZERO, "last": LAST, "extrap": EXTRAP, "proj": PROJ}
+METHODS = {"zero": ZERO, "last": LAST, "extrap": EXTRAP, "proj": PROJ, "spextrap": SPEXTRAP,
+           "projqr": PROJ_QR}
+# method names with an inner-product suffix: "proj_l2", "projqr_l2"
+PROJ_METHODS = ("proj", "projqr", "proj_l2", "projqr_l2")
+
+
+def parse_method(name: str):
+    """(method, inner) of a method name; projection names take an optional "_l2" suffix."""
+    if name.endswith("_l2") and name[:-3] in ("proj", "projqr"):
+        return METHODS[name[:-3]], INNER_L2
+    return METHODS[name], INNER_A
 DTYPES = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16}
 ELEM_BYTES = {F64: 8, F32: 4, F16: 2, BF16: 2}
 
@@ -35,7 +46,7 @@ class GuessError(RuntimeError):
 class guess_opts(C.Structure):
     _fields_ = [("N", C.c_int64), ("M", C.c_int), ("method", C.c_int), ("degree", C.c_int),
                 ("dtype", C.c_int), ("eps_rel", C.c_double), ("op", C.c_void_p),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("inner", C.c_int)]
 
 
 class guess_info(C.Structure):
@@ -43,7 +54,8 @@ class guess_info(C.Structure):
                 ("degree", C.c_int), ("count", C.c_int), ("head", C.c_int),
                 ("last_accepted", C.c_int), ("restarts", C.c_int), ("rejects", C.c_int),
                 ("nonfinite", C.c_int), ("nu", C.c_double), ("nu0", C.c_double),
-                ("form_bytes", C.c_double), ("update_bytes", C.c_double)]
+                ("form_bytes", C.c_double), ("update_bytes", C.c_double),
+                ("drops", C.c_int), ("inner", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -73,7 +85,9 @@ def _load():
         "guess_get_info": (I, [P, C.POINTER(guess_info)]),
         "guess_reset": (I, [P]),
         "guess_extrap_weights": (I, [I, I, C.POINTER(D)]),
+        "guess_spextrap_weights": (I, [I, I, C.POINTER(D)]),
         "guess_history_get": (I, [P, I, I, P]),
+        "guess_proj_factor": (I, [P, C.POINTER(D), C.POINTER(I)]),
         "workload_plane_wave_rhs": (I, [I, I, C.POINTER(I), C.POINTER(D), C.POINTER(D), P, P]),
         "vec_multidot": (I, [I64, I, P, P, C.POINTER(D), P]),
         "vec_combine": (I, [I64, I, P, C.POINTER(D), P, P]),
@@ -95,7 +109,8 @@ EXPORTED = (
     "guess_op_create", "guess_op_destroy", "guess_op_set_stream", "guess_op_size", "op_apply",
     "pcg_solve", "pcg_solve_ex", "guess_create", "guess_create_ex", "guess_destroy",
     "guess_set_stream", "guess_set_op", "guess_workspace_bytes", "guess_form", "guess_update",
-    "guess_get_info", "guess_reset", "guess_extrap_weights", "guess_history_get",
+    "guess_get_info", "guess_reset", "guess_extrap_weights", "guess_spextrap_weights", "guess_history_get",
+    "guess_proj_factor",
     "workload_plane_wave_rhs", "vec_multidot", "vec_combine", "guess_strerror",
     "guess_last_error", "guess_copy_kernel", "guess_profile", "guess_kernel_times",
 )
@@ -176,9 +191,10 @@ def guess_create(N, M, method, degree) -> int:
     return g
 
 
-def guess_create_ex(N, M, method, degree=0, dtype=F64, eps_rel=0.0, op=None, stream=None) -> int:
+def guess_create_ex(N, M, method, degree=0, dtype=F64, eps_rel=0.0, op=None, stream=None,
+                    inner=INNER_A) -> int:
     o = guess_opts(N=N, M=M, method=method, degree=degree, dtype=dtype, eps_rel=eps_rel,
-                   op=op, stream=stream)
+                   op=op, stream=stream, inner=inner)
     out = C.c_void_p()
     _check(_lib.guess_create_ex(C.byref(o), C.byref(out)))
     return out.value
@@ -224,8 +240,25 @@ def guess_extrap_weights(m, k):
     return list(buf)
 
 
+def guess_spextrap_weights(m, k):
+    buf = (C.c_double * k)()
+    _check(_lib.guess_spextrap_weights(m, k, buf))
+    return list(buf)
+
+
 def guess_history_get(g, which, j, out) -> None:
     _check(_lib.guess_history_get(g, which, j, addr(out)))
+
+
+def guess_proj_factor(g):
+    """(d x d) triangular factor R of the projection history (raw solutions = X R)."""
+    import numpy as np
+
+    buf = (C.c_double * (MAX_M * MAX_M))()
+    d = C.c_int(0)
+    _check(_lib.guess_proj_factor(g, buf, C.byref(d)))
+    n = d.value
+    return np.array(buf[: n * n], dtype=np.float64).reshape(n, n)
 
 
 def guess_profile(g, enable=True) -> None:

@@ -60,8 +60,9 @@ class GuessSequence:
         self.N, self.M, self.method, self.degree, self.dtype = N, M, method, degree, dtype
         self.op = op
         self.stream = L.stream_handle(stream)
-        self.handle = L.guess_create_ex(N, M, L.METHODS[method], degree, L.DTYPES[dtype], eps_rel,
-                                        op.handle if op is not None else None, self.stream)
+        meth, inner = L.parse_method(method)
+        self.handle = L.guess_create_ex(N, M, meth, degree, L.DTYPES[dtype], eps_rel,
+                                        op.handle if op is not None else None, self.stream, inner)
 
     def form(self, b: torch.Tensor = None, out: torch.Tensor = None) -> torch.Tensor:
         out = _dev_f64(self.N, b.device if b is not None else "cuda") if out is None else out

@@ -56,11 +56,25 @@ def test_host_weights_match_exact_rationals(L, k):
         assert max(abs(a - b) for a, b in zip(got, ref)) <= 1e-14 * max(1.0, float(extrap.lebesgue(extrap.beta_ls_exact(m, k))))
 
 
+@pytest.mark.parametrize("k", range(1, 17))
+def test_host_sparse_weights_match_exact_rationals(L, k):
+    """Same nonzero pattern as the oracle's exact pivoting (index work: exact), and
+    weights within two roundings of the exact rationals."""
+    for m in range(0, k):
+        got = L.guess_spextrap_weights(m, k)
+        exact = extrap.beta_sparse_exact(m, k)
+        assert [g != 0.0 for g in got] == [b != 0 for b in exact], (m, k)
+        ref = extrap.to_f64(exact)
+        for a, b in zip(got, ref):
+            assert abs(a - b) <= 2.0 ** -52 * abs(b), (m, k)
+
+
 def test_weight_argument_checks(L):
     for m, k in [(-1, 4), (4, 4), (0, 0), (0, 17)]:
-        with pytest.raises(L.GuessError) as e:
-            L.guess_extrap_weights(m, k)
-        assert e.value.code == L.EINVAL
+        for f in (L.guess_extrap_weights, L.guess_spextrap_weights):
+            with pytest.raises(L.GuessError) as e:
+                f(m, k)
+            assert e.value.code == L.EINVAL
 
 
 def test_create_argument_checks(L):
@@ -72,6 +86,9 @@ def test_create_argument_checks(L):
         dict(N=10, M=4, method=L.EXTRAP, degree=-1),
         dict(N=10, M=4, method=7),
         dict(N=10, M=4, method=L.EXTRAP, degree=1, dtype=9),
+        dict(N=10, M=4, method=L.SPEXTRAP, degree=4),
+        dict(N=10, M=17, method=L.PROJ_QR),
+        dict(N=10, M=4, method=L.PROJ, inner=2),
     ]
     for kw in bad:
         with pytest.raises(L.GuessError) as e:
@@ -93,6 +110,8 @@ def test_operator_and_solver_argument_checks(L):
     assert lib.op_apply(None, None, None) == L.EINVAL
     assert lib.guess_form(None, None, None) == L.EINVAL
     assert lib.guess_update(None, None, None) == L.EINVAL
+    d = ctypes.c_int()
+    assert lib.guess_proj_factor(None, None, ctypes.byref(d)) == L.EINVAL
     assert "invalid" in L.guess_strerror(L.EINVAL)
     assert L.guess_strerror(12345) == "unknown status"
 
@@ -104,4 +123,6 @@ def test_workspace_bytes(L):
     assert L.guess_workspace_bytes(N, M, L.EXTRAP, L.F16) == M * N * 2
     assert L.guess_workspace_bytes(N, M, L.LAST, L.F64) == col
     assert L.guess_workspace_bytes(N, M, L.PROJ, L.F64) >= 2 * M * col + N * 8
+    assert L.guess_workspace_bytes(N, M, L.PROJ_QR, L.F64) == L.guess_workspace_bytes(N, M, L.PROJ, L.F64)
+    assert L.guess_workspace_bytes(N, M, L.SPEXTRAP, L.F32) == M * N * 4
     assert L.guess_workspace_bytes(N, M, L.PROJ, 9) == 0

@@ -18,12 +18,13 @@ pytestmark = pytest.mark.gpu
 RAGGED_N = [1, 2, 3, 4, 5, 7, 1023, 1027, 32 ** 3, 33 ** 3 + 2]
 
 
-def _seq(lib, N, M, m, dtype, steps, seed):
+def _seq(lib, N, M, m, dtype, steps, seed, sparse=False):
     import torch
 
     L = lib
-    g = L.guess_create_ex(N, M, L.EXTRAP if M > 1 or m > 0 else L.LAST, m, L.DTYPES[dtype])
-    ref = extrap.ExtrapHistory(M, m, dtype)
+    method = L.SPEXTRAP if sparse else (L.EXTRAP if M > 1 or m > 0 else L.LAST)
+    g = L.guess_create_ex(N, M, method, m, L.DTYPES[dtype])
+    ref = extrap.ExtrapHistory(M, m, dtype, sparse=sparse)
     X = synth.random_vectors(seed, steps, N) * np.linspace(0.5, 2.0, steps)[:, None]
     x0 = torch.empty(N, dtype=torch.float64, device="cuda")
     out = []
@@ -59,6 +60,32 @@ def test_f64_all_shapes(lib, M, m):
     res, _ = _seq(lib, 4099, M, m, "f64", M + 3, seed=100 + M + m)
     for q, (got, want, _) in enumerate(res[1:], start=1):
         assert rel_inf(got, want) <= 1e-12, (M, m, q)
+
+
+@pytest.mark.parametrize("M,m", [(8, 2), (8, 1), (8, 3), (16, 2), (16, 4), (4, 3), (3, 0), (1, 0)])
+@pytest.mark.parametrize("N", [5, 1027, 33 ** 3 + 2])
+def test_sparse_f64_matches_oracle(lib, M, m, N):
+    """Sparse extrapolation (§3.3): the m+1 selected solutions, oldest first."""
+    announce(f"spextrap f64 M={M} m={m} N={N}")
+    res, info = _seq(lib, N, M, m, "f64", M + 3, seed=500 + M + m, sparse=True)
+    for q, (got, want, _) in enumerate(res[1:], start=1):
+        assert rel_inf(got, want) <= 1e-12, (M, m, q)
+    # only the selected slots are read: (m+1) stored vectors + the FP64 guess
+    assert info["form_bytes"] == N * (8.0 * (min(m, M - 1) + 1) + 8.0)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_sparse_lowprec_within_fp32_bound(lib, dtype):
+    announce(f"spextrap {dtype}")
+    M, m = 8, 2
+    res, _ = _seq(lib, 5003, M, m, dtype, M + 2, seed=9, sparse=True)
+    u = 2.0 ** -24
+    for q, (got, want, hist) in enumerate(res[1:], start=1):
+        k = len(hist)
+        beta = extrap.to_f64(extrap.beta_sparse_exact(min(m, k - 1), k))
+        mag = sum(abs(b) * np.abs(h) for b, h in zip(beta, hist))
+        bound = (m + 2) * u * mag + u * np.abs(want) + 1e-300
+        assert_within(got, want, bound, hist, f"spextrap {dtype} step {q}")
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f16", "bf16"])
