@@ -310,6 +310,9 @@ def main():
             one_step(step, True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        for m in methods:
+            inf = L.guess_get_info(ctx[m])
+            stats[m]["history"] = {k: inf[k] for k in ("count", "restarts", "drops", "rejects")}
         for g in list(ctx.values()) + list(sh.values()):
             L.guess_destroy(g)
         return stats, kstat, wall
@@ -330,6 +333,7 @@ def main():
             "pcg_iters_per_step": float(np.mean(S["iters"])),
             "pcg_ms_per_step": S["solve_ms"] / args.steps,
             "max_relres": float(np.max(S["relres"])),
+            "history_after_run": S["history"],
         }
     kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / v[0], "GBps": v[2] / (v[1] * 1e-3) / 1e9,
                    "bytes_per_launch": v[2] / v[0]} for k, v in sorted(kstat.items())}
