@@ -69,12 +69,19 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--n", type=int, default=256)
+    p.add_argument("--workload", choices=("helmholtz", "varcoef"), default="helmholtz",
+                   help="varcoef: -div(kappa grad u) + 10 u, kappa = exp(g), g a unit-variance Gaussian "
+                        "field with correlation length 0.1 (the largest configuration: --n 384 --M 16)")
     p.add_argument("--M", type=int, default=8)
     p.add_argument("--degree", type=int, default=2)
     p.add_argument("--modes", type=int, default=16)
     p.add_argument("--dt", type=float, default=0.005)
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--rtol", type=float, default=1e-8)
+    p.add_argument("--eps-rel", type=float, default=1e-6,
+                   help="projection: relative rejection threshold of a new vector")
+    p.add_argument("--precision-dtypes", default="f32,f16,bf16")
+    p.add_argument("--progress", action="store_true", help="print a line to stderr after every step")
     p.add_argument("--dtype", default="f64", choices=["f64", "f32", "f16", "bf16"])
     p.add_argument("--methods", default="extrap,proj")
     p.add_argument("--maxit", type=int, default=5000)
@@ -218,7 +225,11 @@ def main():
     roof = copy_roof(L)
     n, N, M = args.n, args.n ** 3, args.M
     methods = [m.strip() for m in args.methods.split(",") if m.strip()]
-    op = Operator(n, 10.0)
+    kappa = None
+    if args.workload == "varcoef":
+        kappa = torch.from_numpy(np.exp(synth.gaussian_field(args.seed + 5, n))).cuda()
+    op = Operator(n, 10.0, kappa)
+    del kappa
     params = synth.plane_wave_params(args.seed, args.modes)
     rhs = PlaneWaveRHS(params, n)
     b = torch.empty(N, dtype=torch.float64, device="cuda")
@@ -233,13 +244,13 @@ def main():
         for m in methods:
             meth, inner = L.parse_method(m)
             ctx[m] = L.guess_create_ex(N, 1 if m == "last" else M, meth,
-                                       args.degree if m in ("extrap", "spextrap") else 0, L.DTYPES[dtype], 1e-6,
+                                       args.degree if m in ("extrap", "spextrap") else 0, L.DTYPES[dtype], args.eps_rel,
                                        op.handle, L.stream_handle(), inner)
             L.guess_profile(ctx[m], True)
             xs[m] = torch.zeros(N, dtype=torch.float64, device="cuda")
             if shadow:
                 sh[m] = L.guess_create_ex(N, 1 if m == "last" else M, meth,
-                                          args.degree if m in ("extrap", "spextrap") else 0, L.F64, 1e-6, op.handle,
+                                          args.degree if m in ("extrap", "spextrap") else 0, L.F64, args.eps_rel, op.handle,
                                           L.stream_handle(), inner)
         if shadow:
             x64 = torch.empty(N, dtype=torch.float64, device="cuda")
@@ -304,10 +315,14 @@ def main():
 
         for step in range(1, warmup + 1):
             one_step(step, False)
+            if args.progress:
+                print(f"[bench] {dtype} warm-up step {step} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for step in range(warmup + 1, warmup + steps + 1):
             one_step(step, True)
+            if args.progress:
+                print(f"[bench] {dtype} timed step {step} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         for m in methods:
@@ -350,10 +365,12 @@ def main():
         "vs_baseline": None,
         "dtype": args.dtype,
         "data": "synthetic",
-        "config": {"workload": f"helmholtz7 {n}^3 ({N} unknowns), {args.modes} plane-wave modes, dt={args.dt}, "
+        "config": {"workload": f"{'helmholtz7' if args.workload == 'helmholtz' else 'varcoef7 kappa=exp(GRF l=0.1)'} "
+                               f"{n}^3 ({N} unknowns), {args.modes} plane-wave modes, dt={args.dt}, "
                                f"M={M}, EXTRAP({args.degree},{M}) + PROJ({M}), {args.dtype} history, PCG rtol {args.rtol}",
                    "n": n, "N": N, "M": M, "degree": args.degree, "methods": methods,
-                   "history_dtype": args.dtype, "parallelism": "single GPU"},
+                   "history_dtype": args.dtype, "eps_rel": args.eps_rel, "rtol": args.rtol,
+                   "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": hbm_traffic(dname),
                      "bytes_per_launch": dby / dl, "avg_us": 1e3 * dms / dl,
@@ -363,7 +380,7 @@ def main():
     }
     if args.precision_steps > 0 and args.dtype == "f64":
         prec = {}
-        for dt in ("f32", "f16", "bf16"):
+        for dt in [d.strip() for d in args.precision_dtypes.split(",") if d.strip()]:
             st_, ks_, wall_ = run(dt, args.precision_steps, args.warmup, shadow=True)
             gb = sum(S["guess_bytes"] for S in st_.values())
             gm = sum(S["guess_ms"] for S in st_.values())
