@@ -46,8 +46,11 @@ for _m in ("projqr", "proj_l2", "projqr_l2"):
     KERNELS[(_m, "update")] = KERNELS[("proj", "update")]
 
 
-def kernel_bytes(method, call, N, s, k_or_d, M, restart):
-    """Algorithmic HBM bytes of each kernel of one call (list, launch order)."""
+def kernel_bytes(method, call, N, s, k_or_d, M, restart, faces=0):
+    """Algorithmic HBM bytes of each kernel of one call (list, launch order).
+
+    `faces`: bytes of the operator's face arrays, read by the fused operator
+    apply of a variable-coefficient workload."""
     if method in ("extrap", "last", "spextrap"):
         if call == "form":
             return [N * (k_or_d * s + 8)] if k_or_d > 0 else []
@@ -56,11 +59,11 @@ def kernel_bytes(method, call, N, s, k_or_d, M, restart):
     if call == "form":
         return [N * (d * s + 8) if d > 0 else 0, 0, N * (d * s + 8)]
     if restart:
-        return [N * (8 + 2 * s), 0, 0, 0, 0, 0]
+        return [N * (8 + 2 * s) + faces, 0, 0, 0, 0, 0]
     reorth = N * ((1 if method.endswith("_l2") else 2) * d * s + 8)
     if method.startswith("projqr") and d == M:      # rolling drop: every column rotated in place
-        return [N * (16 + d * s), 0, reorth, 0, N * (4 * d * s + 16), 0]
-    return [N * (16 + d * s), 0, reorth, 0, N * (2 * d * s + 16 + 2 * s), 0]
+        return [N * (16 + d * s) + faces, 0, reorth, 0, N * (4 * d * s + 16), 0]
+    return [N * (16 + d * s) + faces, 0, reorth, 0, N * (2 * d * s + 16 + 2 * s), 0]
 
 
 def parse():
@@ -82,12 +85,16 @@ def parse():
                    help="projection: relative rejection threshold of a new vector")
     p.add_argument("--precision-dtypes", default="f32,f16,bf16")
     p.add_argument("--progress", action="store_true", help="print a line to stderr after every step")
+    p.add_argument("--stop-rule", choices=("rhs", "initresid"), default="rhs",
+                   help="PCG stop: ||r|| <= rtol ||b|| or ||r|| < rtol max(||r0||, 1)")
+    p.add_argument("--rhs", choices=("planewave", "gaussian"), default="planewave",
+                   help="gaussian: a moving Gaussian source (solutions not confined to a low-rank space)")
     p.add_argument("--dtype", default="f64", choices=["f64", "f32", "f16", "bf16"])
     p.add_argument("--methods", default="extrap,proj")
     p.add_argument("--maxit", type=int, default=5000)
     p.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     p.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
-    p.add_argument("--cpu-steps", type=int, default=2)
+    p.add_argument("--cpu-steps", type=int, default=12)
     p.add_argument("--precision-steps", type=int, default=10,
                    help="timed steps of each FP32/FP16/BF16 history run (0: skip)")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -230,8 +237,16 @@ def main():
         kappa = torch.from_numpy(np.exp(synth.gaussian_field(args.seed + 5, n))).cuda()
     op = Operator(n, 10.0, kappa)
     del kappa
+    faces = 8 * 3 * (n + 1) * n * n if args.workload == "varcoef" else 0
     params = synth.plane_wave_params(args.seed, args.modes)
-    rhs = PlaneWaveRHS(params, n)
+    if args.rhs == "planewave":
+        rhs = PlaneWaveRHS(params, n)
+    else:
+        gp = synth.gaussian_source_params(args.seed)
+
+        def rhs(t, out):
+            L.workload_gaussian_rhs(n, synth.gaussian_center(gp, t), gp["sigma"], gp["amp"], out,
+                                    L.stream_handle())
     b = torch.empty(N, dtype=torch.float64, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
@@ -276,7 +291,8 @@ def main():
                     nrm = float(torch.linalg.vector_norm(x64))
                     stats[m]["err"].append(float(torch.linalg.vector_norm(x - x64)) / nrm if nrm > 0 else 0.0)
                 ev[0].record()
-                st, it, rr = op.solve(b, x, args.rtol, args.maxit)
+                st, it, rr = op.solve(b, x, args.rtol, args.maxit,
+                                      L.STOP_RHS if args.stop_rule == "rhs" else L.STOP_INITRESID)
                 ev[1].record()
                 inf1 = L.guess_get_info(g)
                 L.guess_update(g, x)
@@ -299,7 +315,7 @@ def main():
                     restart = m.startswith("proj") and (dd == 0 or dd >= M)
                 for call, times, kdd in (("form", tf, kd_form), ("update", tu, inf1["count"])):
                     names = KERNELS[(m, call)]
-                    byts = kernel_bytes(m, call, N, s, kdd, M, restart)
+                    byts = kernel_bytes(m, call, N, s, kdd, M, restart, faces)
                     for name, ms, by in zip(names, times, byts):
                         # every kernel of the call counts in the guess time; the
                         # per-kernel table keeps the streaming kernels that moved data
@@ -366,10 +382,13 @@ def main():
         "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": f"{'helmholtz7' if args.workload == 'helmholtz' else 'varcoef7 kappa=exp(GRF l=0.1)'} "
-                               f"{n}^3 ({N} unknowns), {args.modes} plane-wave modes, dt={args.dt}, "
+                               f"{n}^3 ({N} unknowns), "
+                               f"{str(args.modes) + ' plane-wave modes' if args.rhs == 'planewave' else 'moving Gaussian source'}"
+                               f", dt={args.dt}, "
                                f"M={M}, EXTRAP({args.degree},{M}) + PROJ({M}), {args.dtype} history, PCG rtol {args.rtol}",
                    "n": n, "N": N, "M": M, "degree": args.degree, "methods": methods,
                    "history_dtype": args.dtype, "eps_rel": args.eps_rel, "rtol": args.rtol,
+                   "stop_rule": args.stop_rule, "rhs": args.rhs,
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": hbm_traffic(dname),

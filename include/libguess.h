@@ -138,6 +138,10 @@ typedef struct guess_opts {
     guess_op_t op;      /* PROJ: operator applied in guess_update when Ax == NULL    */
     void *stream;       /* hipStream_t; NULL = null stream                           */
     int inner;          /* PROJ, PROJ_QR: GUESS_INNER_A (default) or GUESS_INNER_L2  */
+    void *workspace;    /* NULL, or caller device memory, 256-byte aligned, that holds the
+                           history and scratch (guess_workspace_bytes); the library then
+                           allocates no device memory for the context and never frees it */
+    size_t workspace_bytes;
 } guess_opts;
 
 #define GUESS_MAX_M 16
@@ -151,7 +155,8 @@ int guess_create_ex(const guess_opts *o, guess_t *out);
 void guess_destroy(guess_t g);
 int guess_set_stream(guess_t g, void *stream);
 int guess_set_op(guess_t g, guess_op_t A);
-/* Device bytes the history and scratch of such a context occupy. */
+/* Device bytes the history and scratch of such a context occupy (the size a
+ * caller workspace must have; buffers inside it are 256-byte aligned). */
 size_t guess_workspace_bytes(int64_t N, int M, int method, int dtype);
 
 /*
@@ -277,6 +282,17 @@ int guess_kernel_times(guess_t g, double *ms, int max, int *n);
  */
 int workload_plane_wave_rhs(int n, int K, const int *kvec, const double *theta,
                             const double *amp, double *b, void *stream);
+
+/*
+ * Synthetic right-hand side whose solutions are not confined to a fixed
+ * low-dimensional space: a Gaussian source at `center` (host array of 3
+ * coordinates in the unit cube) of width sigma > 0,
+ *   b_i = amp * (g_x(i) * (g_y(j) * g_z(l))),  g_a(i) = exp(-(x_i - c_a)^2 / (2 sigma^2)),
+ * x_i = (i + 1) / (n + 1), on the n^3 interior nodes, x fastest.  b is a
+ * device vector of n^3 doubles; a small per-thread table buffer is kept
+ * between calls.  Enqueued on `stream`; EINVAL for bad arguments.
+ */
+int workload_gaussian_rhs(int n, const double *center, double sigma, double amp, double *b, void *stream);
 
 /* ------------------------------------------------------------------ vectors */
 

@@ -36,7 +36,14 @@ def _pad(u: np.ndarray, n: int) -> np.ndarray:
 def apply_const(u: np.ndarray, n: int, shift: float = 10.0, c: float = None) -> np.ndarray:
     """y = A u for the constant-coefficient operator (-Laplacian_h + shift I)."""
     c = inv_h2(n) if c is None else c
-    P = _pad(u, n)
+    return apply_const_box(u, (n, n, n), c, shift)
+
+
+def apply_const_box(u: np.ndarray, shape, c: float, shift: float = 10.0) -> np.ndarray:
+    """The same operator on an nx x ny x nz box of interior nodes, shape = (nx, ny, nz), x fastest."""
+    nx, ny, nz = shape
+    P = np.zeros((nz + 2, ny + 2, nx + 2), dtype=np.float64)
+    P[1:-1, 1:-1, 1:-1] = np.asarray(u, dtype=np.float64).reshape(nz, ny, nx)
     U = P[1:-1, 1:-1, 1:-1]
     s = 6.0 * U
     s = s - P[1:-1, 1:-1, :-2]   # west

@@ -93,6 +93,13 @@ int reduce_blocks() {
     return v;
 }
 
+// LIBGUESS_MARCH=0 selects the chunk form of PCG's stencil kernel everywhere
+// (for comparisons); the default uses the z-marching form where it applies.
+bool march_enabled() {
+    static const bool v = env_int("LIBGUESS_MARCH", 1) != 0;
+    return v;
+}
+
 }  // namespace lg
 
 // ====================================================================== operator
@@ -399,6 +406,7 @@ struct guess_ctx {
     int64_t N = 0, ld = 0;
     int M = 1, method = GUESS_ZERO, degree = 0, dtype = GUESS_F64, es = 8;
     int inner = GUESS_INNER_A, vf = 0;   // projection: inner product, kernel variant flags
+    bool external = false;               // device buffers carved from the caller's workspace
     double eps_rel = 1e-6;
     guess_op_t op = nullptr;
     hipStream_t stream = nullptr;
@@ -426,8 +434,9 @@ static void ctx_free(guess_ctx *g) {
             (void)hipEventDestroy(g->kev.start[i]);
             (void)hipEventDestroy(g->kev.stop[i]);
         }
-    for (void *ptr : {g->ring, g->X, g->B, (void *)g->w, (void *)g->part, (void *)g->st})
-        if (ptr) (void)hipFree(ptr);
+    if (!g->external)
+        for (void *ptr : {g->ring, g->X, g->B, (void *)g->w, (void *)g->part, (void *)g->st})
+            if (ptr) (void)hipFree(ptr);
     if (g->host_st) (void)hipHostFree(g->host_st);
     delete g;
 }
@@ -437,20 +446,34 @@ static bool ring_method(int method) {
 }
 static bool proj_method(int method) { return method == GUESS_PROJ || method == GUESS_PROJ_QR; }
 
-extern "C" size_t guess_workspace_bytes(int64_t N, int M, int method, int dtype) {
+// Device buffers of a context, in carving order; every one starts 256-byte
+// aligned (sizes rounded up to 256 bytes).
+static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+static int ctx_buffers(int64_t N, int M, int method, int dtype, size_t sizes[6]) {
+    for (int i = 0; i < 6; ++i) sizes[i] = 0;   // ring, X, B, w, part, st
     const int es = esize(dtype);
     if (N < 1 || M < 1 || es == 0) return 0;
     const size_t col = (size_t)col_stride(N) * es;
-    switch (method) {
-        case GUESS_LAST: return col;
-        case GUESS_EXTRAP:
-        case GUESS_SPEXTRAP: return col * M;
-        case GUESS_PROJ:
-        case GUESS_PROJ_QR:
-            return 2 * col * M + (size_t)N * 8 + sizeof(double) * lg::kMaxPartialBlocks * lg::kMaxDots +
-                   sizeof(lg::ProjState);
+    if (method == GUESS_LAST) sizes[0] = col;
+    else if (ring_method(method)) sizes[0] = col * M;
+    else if (proj_method(method)) {
+        sizes[1] = col * M;
+        sizes[2] = col * M;
+        sizes[3] = round256((size_t)N * 8);
+        sizes[4] = round256(sizeof(double) * lg::kMaxPartialBlocks * lg::kMaxDots);
+        sizes[5] = round256(sizeof(lg::ProjState));
     }
-    return 0;
+    return 1;
+}
+
+extern "C" size_t guess_workspace_bytes(int64_t N, int M, int method, int dtype) {
+    if (method == GUESS_LAST) M = 1;
+    size_t sizes[6];
+    ctx_buffers(N, M, method, dtype, sizes);
+    size_t t = 0;
+    for (size_t b : sizes) t += b;
+    return t;
 }
 
 static int proj_upload_state(guess_ctx *g) {
@@ -494,7 +517,27 @@ extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
     g->op = o->op;
     g->stream = (hipStream_t)o->stream;
     const size_t col = (size_t)g->ld * g->es;
+    // caller workspace: carve the buffers in the order of ctx_buffers
+    size_t sizes[6];
+    ctx_buffers(o->N, g->M > 0 ? g->M : 1, o->method, o->dtype, sizes);
+    char *carve = nullptr;
+    if (o->workspace) {
+        size_t need = 0;
+        for (size_t b : sizes) need += b;
+        if (((uintptr_t)o->workspace & 255u) != 0 || o->workspace_bytes < need) {
+            delete g;
+            return fail(GUESS_EINVAL, "guess_create: workspace must be 256-byte aligned and hold " +
+                                          std::to_string(need) + " bytes");
+        }
+        carve = (char *)o->workspace;
+        g->external = true;
+    }
     auto alloc = [&](void **ptr, size_t bytes) -> int {
+        if (carve) {
+            *ptr = carve;
+            carve += round256(bytes);
+            return GUESS_OK;
+        }
         hipError_t e = hipMalloc(ptr, bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -694,6 +737,12 @@ extern "C" int guess_get_info(guess_t g, guess_info *info) {
             if (restart) info->update_bytes = N * (8.0 + 2.0 * es + (g->last_update_ax ? 8.0 : 0.0));
             else if (s.drop) info->update_bytes = N * (16.0 + d * es + reorth + 4.0 * d * es + 16.0);
             else info->update_bytes = N * (16.0 + d * es + reorth + 2.0 * d * es + 16.0 + 2.0 * es);
+            // a variable-coefficient operator applied by the library also reads its face arrays
+            if (!g->last_update_ax && g->op && g->op->g.kx) {
+                const lg::Grid &G = g->op->g;
+                info->update_bytes += 8.0 * ((double)(G.nx + 1) * G.ny * G.nz + (double)G.nx * (G.ny + 1) * G.nz +
+                                             (double)G.nx * G.ny * (G.nz + 1));
+            }
         }
     } else {
         LG_HIP(hipStreamSynchronize(g->stream));
@@ -840,6 +889,35 @@ extern "C" int workload_plane_wave_rhs(int n, int K, const int *kvec, const doub
     const size_t tsz = (size_t)K * n * 2;
     LG_TRY(lg::launch_plane_wave_rhs(n, K, g_pw.dev, g_pw.dev + tsz, g_pw.dev + 2 * tsz, amp, b, s));
     return check_launch("workload_plane_wave_rhs");
+}
+
+namespace {
+struct GaussTables {
+    int n = 0;
+    double *dev = nullptr;
+};
+thread_local GaussTables g_gauss;
+}  // namespace
+
+extern "C" int workload_gaussian_rhs(int n, const double *center, double sigma, double amp, double *b,
+                                     void *stream) {
+    if (n < 1 || !center || !b || !(sigma > 0.0) || !std::isfinite(sigma))
+        return fail(GUESS_EINVAL, "workload_gaussian_rhs: bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (!g_gauss.dev || g_gauss.n < n) {
+        if (g_gauss.dev) {
+            LG_HIP(hipStreamSynchronize(s));
+            (void)hipFree(g_gauss.dev);
+            g_gauss.dev = nullptr;
+        }
+        if (hipMalloc((void **)&g_gauss.dev, sizeof(double) * 3 * (size_t)n) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(GUESS_ENOMEM, "workload_gaussian_rhs: allocation failed");
+        }
+        g_gauss.n = n;
+    }
+    LG_TRY(lg::launch_gaussian_rhs(n, center, sigma, amp, g_gauss.dev, b, s));
+    return check_launch("workload_gaussian_rhs");
 }
 
 // ====================================================================== vectors

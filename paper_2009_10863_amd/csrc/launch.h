@@ -104,9 +104,12 @@ int launch_combine(int64_t N, int K, const double *V, const double *c, double *y
 int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 int launch_plane_wave_rhs(int n, int K, const double *tabx, const double *taby,
                           const double *tabz, const double *amp, double *b, hipStream_t s);
+int launch_gaussian_rhs(int n, const double *center, double sigma, double amp, double *tab, double *b,
+                        hipStream_t s);
 
 // grid-size knob for the streaming kernels (LIBGUESS_GRID_CAP, default below)
 int grid_cap();
 int reduce_blocks();
+bool march_enabled();
 
 }  // namespace lg

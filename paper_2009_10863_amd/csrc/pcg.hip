@@ -106,14 +106,13 @@ LG_REDUCE_KERNEL void pcg_init_kernel(Grid g, const double *__restrict__ b, cons
     block_partials<3>(acc, part, lds);
 }
 
-template <bool VAR, bool AL>
-LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, const double *__restrict__ r, const double *__restrict__ pold,
-                                   double *__restrict__ pnew, double *__restrict__ q,
-                                   const double *part_b, double *part_a, PcgState *st, int k, double rtol) {
-    __shared__ double lds[kLdsDoubles];
-    if (pcg_done(st)) return;
+// Start of iteration k, shared by both forms of pcg_a: the stop test on the
+// rows of r_{k-1} (nb rows of part_b) and beta.  Returns false when the
+// solve stops here.
+__device__ __forceinline__ bool pcg_a_begin(const double *part_b, int nb, PcgState *st, int k, double rtol,
+                                            double *lds, double &beta) {
     double tot[3];
-    final_sums<3>(part_b, gridDim.x, tot, lds);
+    final_sums<3>(part_b, nb, tot, lds);
     const double rr = tot[0], rz = tot[1];
     const double rn = sqrt(rr);
     double thresh;
@@ -134,9 +133,21 @@ LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, const double *__restrict__ r, const d
             st->rho[k & 1] = rz;
         }
     }
-    if (stop) return;
+    if (stop) return false;
+    beta = k == 1 ? 0.0 : rz / st->rho[(k - 1) & 1];
+    return true;
+}
+
+template <bool VAR, bool AL>
+LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, const double *__restrict__ r, const double *__restrict__ pold,
+                                   double *__restrict__ pnew, double *__restrict__ q,
+                                   const double *part_b, int nb_b, double *part_a, PcgState *st, int k,
+                                   double rtol) {
+    __shared__ double lds[kLdsDoubles];
+    if (pcg_done(st)) return;
+    double beta;
+    if (!pcg_a_begin(part_b, nb_b, st, k, rtol, lds, beta)) return;
     const bool first = k == 1;
-    const double beta = first ? 0.0 : rz / st->rho[(k - 1) & 1];
     const PNext<VAR> pn{r, pold, g.dinv, g.dinv_const, beta, first};
     double acc[1] = {0.0};
     const ChunkRange cr = xcd_range(nchunks(g.n));
@@ -159,14 +170,143 @@ LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, const double *__restrict__ r, const d
     block_partials<1>(acc, part_a, lds);
 }
 
+// ------------------------------------------------------------------ z-marching pcg_a
+// Same arithmetic as pcg_a_kernel, different traversal (constant
+// coefficient; every z-plane a whole number of 4-tile groups).  A wave owns
+// one 256-element tile of a z-plane and sweeps it through a range of
+// planes, keeping the search direction of planes z-1, z, z+1 in registers:
+// per step it loads r and p_old once for plane z+1 and for the rows y-1,
+// y+1, and takes the x-neighbours from the adjacent lanes (the tile's first
+// and last element from one extra load when the tile does not start or end
+// a grid row).  The 7-point values, their order and rounding are those of
+// the chunk form, so p and q are bit-identical to it.
+struct March {
+    int tp;      // 256-element tiles per z-plane
+    int zlen;    // planes per work item
+    int items;   // tp * number of plane ranges
+};
+
+static bool march_ok(const Grid &g) {
+    return !g.kx && g.aligned && g.nxy % 256 == 0 && (g.nxy / 256) % kWaves == 0;
+}
+
+static March make_march(const Grid &g) {
+    March m;
+    m.tp = (int)(g.nxy / 256);
+    // about 1024 workgroups of kWaves items each
+    int nr = (1024 * kWaves) / m.tp;
+    nr = nr < 1 ? 1 : (nr > g.nz ? g.nz : nr);
+    m.zlen = (g.nz + nr - 1) / nr;
+    nr = (g.nz + m.zlen - 1) / m.zlen;
+    m.items = m.tp * nr;
+    return m;
+}
+
+static int march_grid(const March &m) {
+    const int wg = (m.items + kWaves - 1) / kWaves;
+    return wg < kMaxPartialBlocks ? wg : kMaxPartialBlocks;
+}
+
+__device__ __forceinline__ R2 sel2(bool keep, const R2 &v) {
+    return R2{{keep ? v.v[0] : 0.0, keep ? v.v[1] : 0.0}};
+}
+
+// q at one element: fixed order west, east, south, north, bottom, top.
+__device__ __forceinline__ double q_const(const Grid &g, double uc, double w, double e, double s_, double n,
+                                          double b, double t) {
+#pragma clang fp contract(off)
+    double s = 6.0 * uc;
+    s = s - w;
+    s = s - e;
+    s = s - s_;
+    s = s - n;
+    s = s - b;
+    s = s - t;
+    const double a = g.c * s;
+    const double bb = g.shift * uc;
+    return a + bb;
+}
+
+LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, const double *__restrict__ r,
+                                         const double *__restrict__ pold, double *__restrict__ pnew,
+                                         double *__restrict__ q, const double *part_b, int nb_b, double *part_a,
+                                         PcgState *st, int k, double rtol) {
+    __shared__ double lds[kLdsDoubles];
+    if (pcg_done(st)) return;
+    double beta;
+    if (!pcg_a_begin(part_b, nb_b, st, k, rtol, lds, beta)) return;
+    const PNext<false> pn{r, pold, nullptr, g.dinv_const, beta, k == 1};
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // consecutive logical workgroups (neighbouring tiles) on one XCD
+    const int nwg = gridDim.x;
+    const int lb = nwg % kXcds == 0 ? (int)(blockIdx.x % kXcds) * (nwg / kXcds) + (int)(blockIdx.x / kXcds)
+                                    : (int)blockIdx.x;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int64_t nxy = g.nxy;
+    double acc[1] = {0.0};
+    for (int item = lb * kWaves + wave; item < m.items; item += nwg * kWaves) {
+        const int tau = item % m.tp, zr = item / m.tp;
+        const int z0 = zr * m.zlen;
+        const int z1 = z0 + m.zlen < nz ? z0 + m.zlen : nz;
+        const int64_t offa = (int64_t)tau * 256 + 2 * lane, offb = offa + 128;
+        const uint32_t ja = fdiv(g.fnx, (uint32_t)offa), jb = fdiv(g.fnx, (uint32_t)offb);
+        const int ia = (int)((uint32_t)offa - ja * (uint32_t)nx), ib = (int)((uint32_t)offb - jb * (uint32_t)nx);
+        const bool hwa = ia > 0, hea = ia + 2 < nx, hwb = ib > 0, heb = ib + 2 < nx;
+        const bool hsa = ja > 0, hna = (int)ja < ny - 1, hsb = jb > 0, hnb = (int)jb < ny - 1;
+        // plane z0 - 1 (bottom neighbours of the first plane) and plane z0
+        int64_t ea = (int64_t)z0 * nxy + offa;
+        const int64_t eprev = z0 > 0 ? ea - nxy : ea;
+        R2 pa_prev = sel2(z0 > 0, pn.two(eprev)), pb_prev = sel2(z0 > 0, pn.two(eprev + 128));
+        R2 pa = pn.two(ea), pb = pn.two(ea + 128);
+        for (int z = z0; z < z1; ++z, ea += nxy) {
+            const bool ht = z + 1 < nz;
+            const int64_t enext = ht ? ea + nxy : ea;
+            const R2 pa_next = sel2(ht, pn.two(enext)), pb_next = sel2(ht, pn.two(enext + 128));
+            const R2 sa = sel2(hsa, pn.two(hsa ? ea - nx : ea)), na = sel2(hna, pn.two(hna ? ea + nx : ea));
+            const R2 sb = sel2(hsb, pn.two(hsb ? ea + 128 - nx : ea + 128));
+            const R2 nb = sel2(hnb, pn.two(hnb ? ea + 128 + nx : ea + 128));
+            // x-neighbours across lanes; the tile's outer neighbours by load
+            double ew = 0.0, ee = 0.0;
+            if (lane == 0 && hwa) ew = pn(ea - 1);
+            if (lane == 63 && heb) ee = pn(ea + 256 - 2 * 63);
+            const double wa_ = __shfl(pa.v[1], (lane + 63) & 63, 64);
+            const double wb_ = __shfl(pb.v[1], (lane + 63) & 63, 64);
+            const double ea_ = __shfl(pa.v[0], (lane + 1) & 63, 64);
+            const double eb_ = __shfl(pb.v[0], (lane + 1) & 63, 64);
+            const double wa = hwa ? (lane > 0 ? wa_ : ew) : 0.0;
+            const double wb = hwb ? (lane > 0 ? wb_ : wa_) : 0.0;
+            const double eaa = hea ? (lane < 63 ? ea_ : eb_) : 0.0;
+            const double ebb = heb ? (lane < 63 ? eb_ : ee) : 0.0;
+            R4 qv;
+            qv.v[0] = q_const(g, pa.v[0], wa, pa.v[1], sa.v[0], na.v[0], pa_prev.v[0], pa_next.v[0]);
+            qv.v[1] = q_const(g, pa.v[1], pa.v[0], eaa, sa.v[1], na.v[1], pa_prev.v[1], pa_next.v[1]);
+            qv.v[2] = q_const(g, pb.v[0], wb, pb.v[1], sb.v[0], nb.v[0], pb_prev.v[0], pb_next.v[0]);
+            qv.v[3] = q_const(g, pb.v[1], pb.v[0], ebb, sb.v[1], nb.v[1], pb_prev.v[1], pb_next.v[1]);
+            __builtin_nontemporal_store(d2{pa.v[0], pa.v[1]}, reinterpret_cast<d2 *>(pnew + ea));
+            __builtin_nontemporal_store(d2{pb.v[0], pb.v[1]}, reinterpret_cast<d2 *>(pnew + ea + 128));
+            __builtin_nontemporal_store(d2{qv.v[0], qv.v[1]}, reinterpret_cast<d2 *>(q + ea));
+            __builtin_nontemporal_store(d2{qv.v[2], qv.v[3]}, reinterpret_cast<d2 *>(q + ea + 128));
+            acc[0] = __builtin_fma(pa.v[0], qv.v[0], acc[0]);
+            acc[0] = __builtin_fma(pa.v[1], qv.v[1], acc[0]);
+            acc[0] = __builtin_fma(pb.v[0], qv.v[2], acc[0]);
+            acc[0] = __builtin_fma(pb.v[1], qv.v[3], acc[0]);
+            pa_prev = pa;
+            pb_prev = pb;
+            pa = pa_next;
+            pb = pb_next;
+        }
+    }
+    block_partials<1>(acc, part_a, lds);
+}
+
 template <bool VAR>
 LG_REDUCE_KERNEL void pcg_b_kernel(Grid g, double *__restrict__ x, double *__restrict__ r,
                                    const double *__restrict__ p, const double *__restrict__ q,
-                                   const double *part_a, double *part_b, PcgState *st, int k) {
+                                   const double *part_a, int nb_a, double *part_b, PcgState *st, int k) {
     __shared__ double lds[kLdsDoubles];
     if (pcg_done(st)) return;
     double tot[1];
-    final_sums<1>(part_a, gridDim.x, tot, lds);
+    final_sums<1>(part_a, nb_a, tot, lds);
     const double pq = tot[0];
     if (!(pq > 0.0) || !isfinite(pq)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -221,8 +361,15 @@ static void pcg_iter_v(const Grid &g, double *x, double *r, double *const p[2], 
     const int gr = pcg_grid(g);
     double *pnew = p[k & 1];
     const double *pold = p[(k - 1) & 1];
-    pcg_a_kernel<VAR, AL><<<gr, kBlock, 0, s>>>(g, r, pold, pnew, q, part_b, part_a, st, k, rtol);
-    pcg_b_kernel<VAR><<<gr, kBlock, 0, s>>>(g, x, r, pnew, q, part_a, part_b, st, k);
+    int ga = gr;
+    if (!VAR && AL && march_ok(g) && march_enabled()) {
+        const March m = make_march(g);
+        ga = march_grid(m);
+        pcg_a_march_kernel<<<ga, kBlock, 0, s>>>(g, m, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
+    } else {
+        pcg_a_kernel<VAR, AL><<<gr, kBlock, 0, s>>>(g, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
+    }
+    pcg_b_kernel<VAR><<<gr, kBlock, 0, s>>>(g, x, r, pnew, q, part_a, ga, part_b, st, k);
 }
 
 int launch_pcg_iter(const Grid &g, double *x, double *r, double *const p[2], double *q, double *part_a,

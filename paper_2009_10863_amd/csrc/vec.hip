@@ -133,4 +133,37 @@ int launch_plane_wave_rhs(int n, int K, const double *tabx, const double *taby, 
     return GUESS_OK;
 }
 
+// Moving Gaussian source: per-axis tables g_a(i) = exp(-(x_i - c_a)^2 / (2 sigma^2)),
+// x_i = (i + 1) / (n + 1), then b = amp * (g_x(i) * (g_y(j) * g_z(l))).
+__global__ void gaussian_tables_kernel(int n, double cx, double cy, double cz, double inv2s2, double *tab) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 3 * n) return;
+    const int axis = t / n, i = t - axis * n;
+    const double x = (i + 1) * (1.0 / (n + 1));
+    const double c = axis == 0 ? cx : (axis == 1 ? cy : cz);
+    const double d = x - c;
+    tab[t] = exp(-(d * d) * inv2s2);
+}
+
+__global__ __launch_bounds__(kBlock) void gaussian_rhs_kernel(int n, const double *__restrict__ tab, double amp,
+                                                             double *__restrict__ b) {
+    const int64_t N = (int64_t)n * n * n;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+        const int i = (int)(p % n);
+        const int j = (int)((p / n) % n);
+        const int l = (int)(p / ((int64_t)n * n));
+        b[p] = amp * (tab[i] * (tab[n + j] * tab[2 * n + l]));
+    }
+}
+
+int launch_gaussian_rhs(int n, const double *center, double sigma, double amp, double *tab, double *b,
+                        hipStream_t s) {
+    const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+    gaussian_tables_kernel<<<(3 * n + 255) / 256, 256, 0, s>>>(n, center[0], center[1], center[2], inv2s2, tab);
+    const int64_t N = (int64_t)n * n * n;
+    gaussian_rhs_kernel<<<stream_grid(N, grid_cap()), kBlock, 0, s>>>(n, tab, amp, b);
+    return GUESS_OK;
+}
+
 }  // namespace lg

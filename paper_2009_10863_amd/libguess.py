@@ -46,7 +46,8 @@ class GuessError(RuntimeError):
 class guess_opts(C.Structure):
     _fields_ = [("N", C.c_int64), ("M", C.c_int), ("method", C.c_int), ("degree", C.c_int),
                 ("dtype", C.c_int), ("eps_rel", C.c_double), ("op", C.c_void_p),
-                ("stream", C.c_void_p), ("inner", C.c_int)]
+                ("stream", C.c_void_p), ("inner", C.c_int), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t)]
 
 
 class guess_info(C.Structure):
@@ -89,6 +90,7 @@ def _load():
         "guess_history_get": (I, [P, I, I, P]),
         "guess_proj_factor": (I, [P, C.POINTER(D), C.POINTER(I)]),
         "workload_plane_wave_rhs": (I, [I, I, C.POINTER(I), C.POINTER(D), C.POINTER(D), P, P]),
+        "workload_gaussian_rhs": (I, [I, C.POINTER(D), D, D, P, P]),
         "vec_multidot": (I, [I64, I, P, P, C.POINTER(D), P]),
         "vec_combine": (I, [I64, I, P, C.POINTER(D), P, P]),
         "guess_strerror": (C.c_char_p, [I]),
@@ -111,7 +113,7 @@ EXPORTED = (
     "guess_set_stream", "guess_set_op", "guess_workspace_bytes", "guess_form", "guess_update",
     "guess_get_info", "guess_reset", "guess_extrap_weights", "guess_spextrap_weights", "guess_history_get",
     "guess_proj_factor",
-    "workload_plane_wave_rhs", "vec_multidot", "vec_combine", "guess_strerror",
+    "workload_plane_wave_rhs", "workload_gaussian_rhs", "vec_multidot", "vec_combine", "guess_strerror",
     "guess_last_error", "guess_copy_kernel", "guess_profile", "guess_kernel_times",
 )
 
@@ -192,9 +194,14 @@ def guess_create(N, M, method, degree) -> int:
 
 
 def guess_create_ex(N, M, method, degree=0, dtype=F64, eps_rel=0.0, op=None, stream=None,
-                    inner=INNER_A) -> int:
+                    inner=INNER_A, workspace=None) -> int:
+    """workspace: None, or a device tensor (or address) of at least guess_workspace_bytes
+    bytes, 256-byte aligned, that holds the context's device buffers; it must outlive the context."""
+    nbytes = 0
+    if workspace is not None and not isinstance(workspace, int):
+        nbytes = workspace.numel() * workspace.element_size()
     o = guess_opts(N=N, M=M, method=method, degree=degree, dtype=dtype, eps_rel=eps_rel,
-                   op=op, stream=stream, inner=inner)
+                   op=op, stream=stream, inner=inner, workspace=addr(workspace), workspace_bytes=nbytes)
     out = C.c_void_p()
     _check(_lib.guess_create_ex(C.byref(o), C.byref(out)))
     return out.value
@@ -280,6 +287,11 @@ def workload_plane_wave_rhs(n, kvec, theta, amp, b, stream=None) -> None:
     th = (C.c_double * K)(*[float(v) for v in theta])
     am = (C.c_double * K)(*[float(v) for v in amp])
     _check(_lib.workload_plane_wave_rhs(n, K, kv, th, am, addr(b), stream))
+
+
+def workload_gaussian_rhs(n, center, sigma, amp, b, stream=None) -> None:
+    c = (C.c_double * 3)(*[float(v) for v in center])
+    _check(_lib.workload_gaussian_rhs(n, c, float(sigma), float(amp), addr(b), stream))
 
 
 def vec_multidot(N, K, V, y, stream=None):

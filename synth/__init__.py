@@ -112,6 +112,33 @@ def plane_wave_rhs_at(params: dict, n: int, t: float, flat_idx, c=None) -> np.nd
     return out
 
 
+# --------------------------------------------------------------------------
+# moving Gaussian source (solutions not confined to a fixed low-rank space)
+# --------------------------------------------------------------------------
+def gaussian_source_params(seed: int, sigma: float = 0.08, radius: float = 0.25, amp: float = 1.0e3) -> dict:
+    """Center path ``c(t) = 0.5 + radius * sin(om * t + ph)`` per axis, ``om ~ U[1, 5]``,
+    ``ph ~ U[0, 2 pi)``, drawn in that order."""
+    rng = np.random.default_rng(seed)
+    om = rng.uniform(1.0, 5.0, 3)
+    ph = rng.uniform(0.0, TWO_PI, 3)
+    return {"omega": om, "phi": ph, "sigma": float(sigma), "radius": float(radius), "amp": float(amp)}
+
+
+def gaussian_center(params: dict, t: float) -> np.ndarray:
+    return 0.5 + params["radius"] * np.sin(params["omega"] * t + params["phi"])
+
+
+def gaussian_source_rhs(params: dict, n: int, t: float) -> np.ndarray:
+    """``b = amp * (g_x(i) * (g_y(j) * g_z(l)))``, ``g_a = exp(-(x - c_a)^2 / (2 sigma^2))``
+    at the interior nodes ``x_i = (i + 1) / (n + 1)``, x fastest."""
+    c = gaussian_center(params, t)
+    x = (np.arange(n, dtype=np.float64) + 1.0) * (1.0 / (n + 1))
+    inv2s2 = 1.0 / (2.0 * params["sigma"] * params["sigma"])
+    g = [np.exp(-((x - c[a]) * (x - c[a])) * inv2s2) for a in range(3)]
+    yz = g[1][None, :, None] * g[2][:, None, None]
+    return (params["amp"] * (g[0][None, None, :] * yz)).reshape(-1)
+
+
 def step_times(T: int, dt: float) -> np.ndarray:
     """``t_n = n dt`` for n = 1..T."""
     return np.arange(1, T + 1, dtype=np.float64) * dt

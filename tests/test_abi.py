@@ -126,3 +126,16 @@ def test_workspace_bytes(L):
     assert L.guess_workspace_bytes(N, M, L.PROJ_QR, L.F64) == L.guess_workspace_bytes(N, M, L.PROJ, L.F64)
     assert L.guess_workspace_bytes(N, M, L.SPEXTRAP, L.F32) == M * N * 4
     assert L.guess_workspace_bytes(N, M, L.PROJ, 9) == 0
+
+
+def test_workspace_route_argument_checks(L):
+    """A caller workspace that is too small or misaligned is refused before any allocation."""
+    lib = L.lib()
+    need = L.guess_workspace_bytes(1000, 4, L.PROJ, L.F64)
+    assert need % 256 == 0
+    o = L.guess_opts(N=1000, M=4, method=L.PROJ, degree=0, dtype=L.F64, eps_rel=0.0, op=None, stream=None,
+                     inner=0, workspace=4096, workspace_bytes=need - 1)
+    out = ctypes.c_void_p()
+    assert lib.guess_create_ex(ctypes.byref(o), ctypes.byref(out)) == L.EINVAL and not out.value
+    o.workspace, o.workspace_bytes = 4096 + 8, need
+    assert lib.guess_create_ex(ctypes.byref(o), ctypes.byref(out)) == L.EINVAL and not out.value

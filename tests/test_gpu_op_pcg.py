@@ -78,6 +78,60 @@ def test_pcg_iterations_and_solution(lib, n, seed):
     assert rel_inf(xg, xo) <= 1e-6
 
 
+BOXES = [(384, 8, 6), (512, 2, 5), (64, 16, 9), (6, 10, 7), (256, 4, 3)]
+
+
+@pytest.mark.parametrize("shape", BOXES)
+def test_box_operator_bit_exact(lib, shape):
+    """Non-cubic grids: rows longer than a 256-element tile, tiles spanning several rows."""
+    import torch
+
+    announce(f"op box {shape}")
+    L = lib
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    A = L.guess_op_create(nx, ny, nz, 900.0, 10.0, None)
+    try:
+        x = synth.random_vectors(nx + ny, 1, N)[0]
+        y = torch.empty(N, dtype=torch.float64, device="cuda")
+        L.op_apply(A, dev(x), y)
+        got = host(y)
+    finally:
+        L.guess_op_destroy(A)
+    assert np.array_equal(got, op.apply_const_box(x, shape, 900.0))
+
+
+@pytest.mark.parametrize("shape", BOXES)
+def test_pcg_box_grids(lib, shape):
+    """PCG on boxes (the z-marching stencil kernel runs where every plane is a whole number of
+    4-tile groups): the first iterates agree with the oracle's to rounding, the converged
+    iteration count to +-1."""
+    import torch
+
+    announce(f"pcg box {shape}")
+    L = lib
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    c = 900.0
+    b = synth.random_vectors(3 * nz, 1, N)[0]
+    apply = lambda v: op.apply_const_box(v, shape, c)  # noqa: E731
+    dinv = np.full(N, 1.0 / (c * 6.0 + 10.0))
+    A = L.guess_op_create(nx, ny, nz, c, 10.0, None)
+    try:
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        st, it, _ = L.pcg_solve(A, dev(b), x, 1e-30, 5)
+        assert st == L.ENOTCONV and it == 5
+        xo, _, _, _ = oracle_pcg(apply, b, np.zeros(N), dinv, 1e-30, 5)
+        assert rel_inf(host(x), xo) <= 1e-11
+        x.zero_()
+        st, it, rr = L.pcg_solve(A, dev(b), x, 1e-8, 5000)
+        xo, ito, sto, _ = oracle_pcg(apply, b, np.zeros(N), dinv, 1e-8, 5000)
+        assert st == L.OK and sto == 0 and abs(it - ito) <= 1
+        assert np.linalg.norm(b - apply(host(x))) <= 1.5e-8 * np.linalg.norm(b)
+    finally:
+        L.guess_op_destroy(A)
+
+
 def test_pcg_varcoef(lib):
     import torch
 
