@@ -248,8 +248,14 @@ extern "C" int pcg_solve_ex(guess_op_t A, const double *b, double *x, double rto
     if (!(A->host_st->converged | A->host_st->breakdown)) {
         lg::launch_pcg_check(A->g, A->part_b, A->st, k, rtol, s);
         LG_TRY(check_launch("pcg_check"));
-        LG_TRY(read_state());
     }
+    // x += alpha p of the last iteration unless a later pcg_a applied it
+    // (a no-op on the device when nothing is pending)
+    if (k > 1) {
+        lg::launch_pcg_finish(A->g, x, A->p[(k - 1) & 1], A->st, s);
+        LG_TRY(check_launch("pcg_finish"));
+    }
+    LG_TRY(read_state());
     const lg::PcgState &st = *A->host_st;
     const int its = (st.converged | st.breakdown) ? st.it : maxit;
     if (iters) *iters = its;

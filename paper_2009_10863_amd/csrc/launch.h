@@ -60,6 +60,7 @@ struct PcgState {
     double rho[2];
     double alpha, rr, bb, rr0, thresh;
     int it, converged, breakdown, rule;
+    int x_pending;          // x still lacks alpha_k p_k of the last completed iteration
 };
 
 // ---- extrapolation (extrap.hip)
@@ -95,6 +96,7 @@ int launch_pcg_init(const Grid &g, const double *b, const double *x, double *r, 
 int launch_pcg_iter(const Grid &g, double *x, double *r, double *const p[2], double *q, double *part_a,
                     double *part_b, PcgState *st, int k, double rtol, hipStream_t s);
 int launch_pcg_check(const Grid &g, const double *part_b, PcgState *st, int k, double rtol, hipStream_t s);
+int launch_pcg_finish(const Grid &g, double *x, const double *p, PcgState *st, hipStream_t s);
 int pcg_grid(const Grid &g);
 
 // ---- vectors and workload (vec.hip)

@@ -23,14 +23,18 @@ static __device__ __forceinline__ V4 toV(const R4 &r) { return V4{{r.v[0], r.v[1
 // identical scalars without any cross-workgroup synchronisation.
 //
 //   pcg_a(k): from rows (r^T r, r^T z, b^T b) of r_{k-1}: stop test (k = 1:
-//             also the threshold); rho_k = r^T z; beta = rho_k / rho_{k-1};
-//             p_k = z + beta p_{k-1} formed on the fly at the stencil points
-//             (z = D^{-1} r), stored, and q = A p_k; rows: p_k^T q.
-//   pcg_b(k): alpha = rho_k / p_k^T q; x += alpha p_k; r -= alpha q;
-//             rows: (r^T r, r^T z, 0).
-// Per iteration: reads r, p_{k-1} (pcg_a, 16 B/unknown), x, r, p_k, q
-// (pcg_b, 32 B); writes p_k, q, x, r (32 B): 80 B per unknown (constant
+//             also the threshold); for k > 1 first x += alpha_{k-1} p_{k-1}
+//             (the update of the previous iteration, deferred to the pass
+//             that reads p_{k-1} anyway); rho_k = r^T z; beta = rho_k /
+//             rho_{k-1}; p_k = z + beta p_{k-1} formed on the fly at the
+//             stencil points (z = D^{-1} r), stored, and q = A p_k;
+//             rows: p_k^T q.
+//   pcg_b(k): alpha = rho_k / p_k^T q; r -= alpha q; rows: (r^T r, r^T z, 0).
+//   pcg_finish: after the last iteration, the pending x update if any.
+// Per iteration: reads r, p_{k-1}, x (pcg_a, 24 B/unknown), r, q (pcg_b,
+// 16 B); writes x, p_k, q, r (32 B): 72 B per unknown (constant
 // coefficient).  p_k and p_{k-1} live in two buffers used alternately.
+// x receives exactly the same FMAs as in the textbook order.
 int pcg_grid(const Grid &g) { return stream_grid(nchunks(g.n), reduce_blocks()); }
 
 __device__ __forceinline__ bool pcg_done(const PcgState *st) { return st->converged | st->breakdown; }
@@ -138,15 +142,38 @@ __device__ __forceinline__ bool pcg_a_begin(const double *part_b, int nb, PcgSta
     return true;
 }
 
+// x += alpha p over the whole vector (the deferred update when the solve
+// stops in pcg_a, and pcg_finish).
+__device__ __forceinline__ void x_update_all(const Grid &g, double *__restrict__ x, const double *__restrict__ p,
+                                             double alpha) {
+    const int64_t nc = nchunks(g.n), stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
+        V4 xv = load4<GUESS_F64>(x, c);
+        const V4 pv = load4<GUESS_F64>(p, c);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xv.v[e] = __builtin_fma(alpha, pv.v[e], xv.v[e]);
+        store4<GUESS_F64>(x, c, xv);
+    }
+    if (blockIdx.x == 0 && threadIdx.x < tail_count(g.n)) {
+        const int64_t t = tail_start(g.n) + threadIdx.x;
+        x[t] = __builtin_fma(alpha, p[t], x[t]);
+    }
+}
+
 template <bool VAR, bool AL>
-LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, const double *__restrict__ r, const double *__restrict__ pold,
-                                   double *__restrict__ pnew, double *__restrict__ q,
-                                   const double *part_b, int nb_b, double *part_a, PcgState *st, int k,
-                                   double rtol) {
+LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, double *__restrict__ x, const double *__restrict__ r,
+                                   const double *__restrict__ pold, double *__restrict__ pnew,
+                                   double *__restrict__ q, const double *part_b, int nb_b, double *part_a,
+                                   PcgState *st, int k, double rtol) {
     __shared__ double lds[kLdsDoubles];
     if (pcg_done(st)) return;
     double beta;
-    if (!pcg_a_begin(part_b, nb_b, st, k, rtol, lds, beta)) return;
+    const double alpha = k > 1 ? st->alpha : 0.0;   // alpha_{k-1}
+    if (k > 1 && blockIdx.x == 0 && threadIdx.x == 0) st->x_pending = 0;
+    if (!pcg_a_begin(part_b, nb_b, st, k, rtol, lds, beta)) {
+        if (k > 1) x_update_all(g, x, pold, alpha);
+        return;
+    }
     const bool first = k == 1;
     const PNext<VAR> pn{r, pold, g.dinv, g.dinv_const, beta, first};
     double acc[1] = {0.0};
@@ -158,11 +185,19 @@ LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, const double *__restrict__ r, const d
         store4<GUESS_F64>(q, c, toV(qv));
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(pc.v[e], qv.v[e], acc[0]);
+        if (!first) {
+            V4 xv = load4<GUESS_F64>(x, c);
+            const V4 pv = load4<GUESS_F64>(pold, c);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xv.v[e] = __builtin_fma(alpha, pv.v[e], xv.v[e]);
+            store4<GUESS_F64>(x, c, xv);
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x < tail_count(g.n)) {
         const int64_t t = tail_start(g.n) + threadIdx.x;
         const double pt = pn(t);
         const double qt = apply_pt<VAR>(pn, g, t);
+        if (!first) x[t] = __builtin_fma(alpha, pold[t], x[t]);
         pnew[t] = pt;
         q[t] = qt;
         acc[0] = __builtin_fma(pt, qt, acc[0]);
@@ -227,15 +262,21 @@ __device__ __forceinline__ double q_const(const Grid &g, double uc, double w, do
     return a + bb;
 }
 
-LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, const double *__restrict__ r,
+LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, double *__restrict__ x, const double *__restrict__ r,
                                          const double *__restrict__ pold, double *__restrict__ pnew,
                                          double *__restrict__ q, const double *part_b, int nb_b, double *part_a,
                                          PcgState *st, int k, double rtol) {
     __shared__ double lds[kLdsDoubles];
     if (pcg_done(st)) return;
     double beta;
-    if (!pcg_a_begin(part_b, nb_b, st, k, rtol, lds, beta)) return;
-    const PNext<false> pn{r, pold, nullptr, g.dinv_const, beta, k == 1};
+    const double alpha = k > 1 ? st->alpha : 0.0;   // alpha_{k-1}
+    if (k > 1 && blockIdx.x == 0 && threadIdx.x == 0) st->x_pending = 0;
+    if (!pcg_a_begin(part_b, nb_b, st, k, rtol, lds, beta)) {
+        if (k > 1) x_update_all(g, x, pold, alpha);
+        return;
+    }
+    const bool first = k == 1;
+    const PNext<false> pn{r, pold, nullptr, g.dinv_const, beta, first};
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     // consecutive logical workgroups (neighbouring tiles) on one XCD
     const int nwg = gridDim.x;
@@ -282,6 +323,15 @@ LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, const double *__restri
             qv.v[1] = q_const(g, pa.v[1], pa.v[0], eaa, sa.v[1], na.v[1], pa_prev.v[1], pa_next.v[1]);
             qv.v[2] = q_const(g, pb.v[0], wb, pb.v[1], sb.v[0], nb.v[0], pb_prev.v[0], pb_next.v[0]);
             qv.v[3] = q_const(g, pb.v[1], pb.v[0], ebb, sb.v[1], nb.v[1], pb_prev.v[1], pb_next.v[1]);
+            if (!first) {
+                // deferred x += alpha_{k-1} p_{k-1} on this plane's pairs
+                const R2 xa = ld2(x, ea), xb = ld2(x, ea + 128);
+                const R2 oa = ld2(pold, ea), ob = ld2(pold, ea + 128);
+                __builtin_nontemporal_store(d2{__builtin_fma(alpha, oa.v[0], xa.v[0]), __builtin_fma(alpha, oa.v[1], xa.v[1])},
+                                            reinterpret_cast<d2 *>(x + ea));
+                __builtin_nontemporal_store(d2{__builtin_fma(alpha, ob.v[0], xb.v[0]), __builtin_fma(alpha, ob.v[1], xb.v[1])},
+                                            reinterpret_cast<d2 *>(x + ea + 128));
+            }
             __builtin_nontemporal_store(d2{pa.v[0], pa.v[1]}, reinterpret_cast<d2 *>(pnew + ea));
             __builtin_nontemporal_store(d2{pb.v[0], pb.v[1]}, reinterpret_cast<d2 *>(pnew + ea + 128));
             __builtin_nontemporal_store(d2{qv.v[0], qv.v[1]}, reinterpret_cast<d2 *>(q + ea));
@@ -300,8 +350,7 @@ LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, const double *__restri
 }
 
 template <bool VAR>
-LG_REDUCE_KERNEL void pcg_b_kernel(Grid g, double *__restrict__ x, double *__restrict__ r,
-                                   const double *__restrict__ p, const double *__restrict__ q,
+LG_REDUCE_KERNEL void pcg_b_kernel(Grid g, double *__restrict__ r, const double *__restrict__ q,
                                    const double *part_a, int nb_a, double *part_b, PcgState *st, int k) {
     __shared__ double lds[kLdsDoubles];
     if (pcg_done(st)) return;
@@ -316,25 +365,25 @@ LG_REDUCE_KERNEL void pcg_b_kernel(Grid g, double *__restrict__ x, double *__res
         return;
     }
     const double alpha = st->rho[k & 1] / pq;
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->alpha = alpha;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->alpha = alpha;
+        st->x_pending = 1;
+    }
     double acc[3] = {0.0, 0.0, 0.0};
     const int64_t nc = nchunks(g.n), stride = (int64_t)gridDim.x * kBlock;
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
-        V4 xv = load4<GUESS_F64>(x, c), rv = load4<GUESS_F64>(r, c);
-        const V4 pv = load4<GUESS_F64>(p, c), qv = load4<GUESS_F64>(q, c), dv = dinv4<VAR>(g, c);
+        V4 rv = load4<GUESS_F64>(r, c);
+        const V4 qv = load4<GUESS_F64>(q, c), dv = dinv4<VAR>(g, c);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            xv.v[e] = __builtin_fma(alpha, pv.v[e], xv.v[e]);
             rv.v[e] = __builtin_fma(-alpha, qv.v[e], rv.v[e]);
             acc[0] = __builtin_fma(rv.v[e], rv.v[e], acc[0]);
             acc[1] = __builtin_fma(rv.v[e], dv.v[e] * rv.v[e], acc[1]);
         }
-        store4<GUESS_F64>(x, c, xv);
         store4<GUESS_F64>(r, c, rv);
     }
     if (blockIdx.x == 0 && threadIdx.x < tail_count(g.n)) {
         const int64_t t = tail_start(g.n) + threadIdx.x;
-        x[t] = __builtin_fma(alpha, p[t], x[t]);
         const double rt = __builtin_fma(-alpha, q[t], r[t]);
         r[t] = rt;
         acc[0] = __builtin_fma(rt, rt, acc[0]);
@@ -365,11 +414,11 @@ static void pcg_iter_v(const Grid &g, double *x, double *r, double *const p[2], 
     if (!VAR && AL && march_ok(g) && march_enabled()) {
         const March m = make_march(g);
         ga = march_grid(m);
-        pcg_a_march_kernel<<<ga, kBlock, 0, s>>>(g, m, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
+        pcg_a_march_kernel<<<ga, kBlock, 0, s>>>(g, m, x, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
     } else {
-        pcg_a_kernel<VAR, AL><<<gr, kBlock, 0, s>>>(g, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
+        pcg_a_kernel<VAR, AL><<<gr, kBlock, 0, s>>>(g, x, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
     }
-    pcg_b_kernel<VAR><<<gr, kBlock, 0, s>>>(g, x, r, pnew, q, part_a, ga, part_b, st, k);
+    pcg_b_kernel<VAR><<<gr, kBlock, 0, s>>>(g, r, q, part_a, ga, part_b, st, k);
 }
 
 int launch_pcg_iter(const Grid &g, double *x, double *r, double *const p[2], double *q, double *part_a,
@@ -410,6 +459,17 @@ __global__ __launch_bounds__(kBlock) void pcg_check_kernel(const double *part_b,
 
 int launch_pcg_check(const Grid &g, const double *part_b, PcgState *st, int k, double rtol, hipStream_t s) {
     pcg_check_kernel<<<1, kBlock, 0, s>>>(part_b, pcg_grid(g), st, k, rtol);
+    return GUESS_OK;
+}
+
+// The x update of the last completed iteration when no later pcg_a applied it.
+__global__ __launch_bounds__(kBlock) void pcg_finish_kernel(Grid g, double *x, const double *p, PcgState *st) {
+    if (!st->x_pending) return;
+    x_update_all(g, x, p, st->alpha);
+}
+
+int launch_pcg_finish(const Grid &g, double *x, const double *p, PcgState *st, hipStream_t s) {
+    pcg_finish_kernel<<<stream_grid(nchunks(g.n) > 0 ? nchunks(g.n) : 1, grid_cap()), kBlock, 0, s>>>(g, x, p, st);
     return GUESS_OK;
 }
 
