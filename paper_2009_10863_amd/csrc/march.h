@@ -1,0 +1,131 @@
+// z-marching traversal for the constant-coefficient 7-point stencil.
+//
+// Applies where every z-plane is a whole number of 4-tile groups (nx even,
+// nx*ny a multiple of 1024).  A wave owns one 256-element tile of a z-plane
+// (the same lane layout as the chunk form of common.h: lane L holds the
+// pairs (2L, 2L+1) and (128+2L, 129+2L)) and sweeps it through a range of
+// planes, keeping the operand of planes z-1, z, z+1 in registers.  Per plane
+// it loads the operand once for plane z+1 and for the rows y-1, y+1, and
+// takes the x-neighbours from the adjacent lanes; only the tile's first and
+// last element may need one extra load (when the tile does not start or end
+// a grid row).  The four workgroup waves own four consecutive tiles, and
+// consecutive workgroups are placed on one XCD, so the y-neighbour rows are
+// mostly read from that XCD's L2.
+//
+// Each point is evaluated with the fixed order of the chunk form (west,
+// east, south, north, bottom, top, no contraction, then c*s + shift*u), so
+// results are bit-identical to it; only the traversal differs.
+#pragma once
+
+#include "common.h"
+#include "stencil.h"
+
+namespace lg {
+
+struct March {
+    int tp;      // 256-element tiles per z-plane
+    int zlen;    // planes per work item
+    int items;   // tp * number of plane ranges
+};
+
+inline bool march_ok(const Grid &g) {
+    return !g.kx && g.aligned && g.nxy % 256 == 0 && (g.nxy / 256) % kWaves == 0;
+}
+
+inline March make_march(const Grid &g) {
+    March m;
+    m.tp = (int)(g.nxy / 256);
+    // about 1024 workgroups of kWaves items each
+    int nr = (1024 * kWaves) / m.tp;
+    nr = nr < 1 ? 1 : (nr > g.nz ? g.nz : nr);
+    m.zlen = (g.nz + nr - 1) / nr;
+    nr = (g.nz + m.zlen - 1) / m.zlen;
+    m.items = m.tp * nr;
+    return m;
+}
+
+inline int march_grid(const March &m) {
+    const int wg = (m.items + kWaves - 1) / kWaves;
+    return wg < kMaxPartialBlocks ? wg : kMaxPartialBlocks;
+}
+
+__device__ __forceinline__ R2 sel2(bool keep, const R2 &v) {
+    return R2{{keep ? v.v[0] : 0.0, keep ? v.v[1] : 0.0}};
+}
+
+// (A u) at one element: fixed order west, east, south, north, bottom, top.
+__device__ __forceinline__ double q_const(const Grid &g, double uc, double w, double e, double s_, double n,
+                                          double b, double t) {
+#pragma clang fp contract(off)
+    double s = 6.0 * uc;
+    s = s - w;
+    s = s - e;
+    s = s - s_;
+    s = s - n;
+    s = s - b;
+    s = s - t;
+    const double a = g.c * s;
+    const double bb = g.shift * uc;
+    return a + bb;
+}
+
+// Sweep the wave's work items.  U: operand access (u(q), u.two(q) as in
+// stencil.h).  f(c, e, ua, ub, au) is called once per chunk with its chunk
+// index c (as in common.h), the flat index e of its first pair, the centre
+// values of both pairs and A u at the chunk's four elements.
+template <class U, class F>
+__device__ __forceinline__ void march_sweep(const Grid &g, const March &m, const U &u, F &&f) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwg = gridDim.x;
+    const int lb = nwg % kXcds == 0 ? (int)(blockIdx.x % kXcds) * (nwg / kXcds) + (int)(blockIdx.x / kXcds)
+                                    : (int)blockIdx.x;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int64_t nxy = g.nxy;
+    for (int item = lb * kWaves + wave; item < m.items; item += nwg * kWaves) {
+        const int tau = item % m.tp, zr = item / m.tp;
+        const int z0 = zr * m.zlen;
+        const int z1 = z0 + m.zlen < nz ? z0 + m.zlen : nz;
+        const int64_t offa = (int64_t)tau * 256 + 2 * lane, offb = offa + 128;
+        const uint32_t ja = fdiv(g.fnx, (uint32_t)offa), jb = fdiv(g.fnx, (uint32_t)offb);
+        const int ia = (int)((uint32_t)offa - ja * (uint32_t)nx), ib = (int)((uint32_t)offb - jb * (uint32_t)nx);
+        const bool hwa = ia > 0, hea = ia + 2 < nx, hwb = ib > 0, heb = ib + 2 < nx;
+        const bool hsa = ja > 0, hna = (int)ja < ny - 1, hsb = jb > 0, hnb = (int)jb < ny - 1;
+        int64_t ea = (int64_t)z0 * nxy + offa;
+        int64_t c = ((int64_t)z0 * m.tp + tau) * 64 + lane;
+        const int64_t eprev = z0 > 0 ? ea - nxy : ea;
+        R2 pa_prev = sel2(z0 > 0, u.two(eprev)), pb_prev = sel2(z0 > 0, u.two(eprev + 128));
+        R2 pa = u.two(ea), pb = u.two(ea + 128);
+        for (int z = z0; z < z1; ++z, ea += nxy, c += (int64_t)m.tp * 64) {
+            const bool ht = z + 1 < nz;
+            const int64_t enext = ht ? ea + nxy : ea;
+            const R2 pa_next = sel2(ht, u.two(enext)), pb_next = sel2(ht, u.two(enext + 128));
+            const R2 sa = sel2(hsa, u.two(hsa ? ea - nx : ea)), na = sel2(hna, u.two(hna ? ea + nx : ea));
+            const R2 sb = sel2(hsb, u.two(hsb ? ea + 128 - nx : ea + 128));
+            const R2 nb = sel2(hnb, u.two(hnb ? ea + 128 + nx : ea + 128));
+            // x-neighbours across lanes; the tile's outer neighbours by load
+            double ew = 0.0, ee = 0.0;
+            if (lane == 0 && hwa) ew = u(ea - 1);
+            if (lane == 63 && heb) ee = u(ea + 256 - 2 * 63);
+            const double wa_ = __shfl(pa.v[1], (lane + 63) & 63, 64);
+            const double wb_ = __shfl(pb.v[1], (lane + 63) & 63, 64);
+            const double ea_ = __shfl(pa.v[0], (lane + 1) & 63, 64);
+            const double eb_ = __shfl(pb.v[0], (lane + 1) & 63, 64);
+            const double wa = hwa ? (lane > 0 ? wa_ : ew) : 0.0;
+            const double wb = hwb ? (lane > 0 ? wb_ : wa_) : 0.0;
+            const double eaa = hea ? (lane < 63 ? ea_ : eb_) : 0.0;
+            const double ebb = heb ? (lane < 63 ? eb_ : ee) : 0.0;
+            R4 au;
+            au.v[0] = q_const(g, pa.v[0], wa, pa.v[1], sa.v[0], na.v[0], pa_prev.v[0], pa_next.v[0]);
+            au.v[1] = q_const(g, pa.v[1], pa.v[0], eaa, sa.v[1], na.v[1], pa_prev.v[1], pa_next.v[1]);
+            au.v[2] = q_const(g, pb.v[0], wb, pb.v[1], sb.v[0], nb.v[0], pb_prev.v[0], pb_next.v[0]);
+            au.v[3] = q_const(g, pb.v[1], pb.v[0], ebb, sb.v[1], nb.v[1], pb_prev.v[1], pb_next.v[1]);
+            f(c, ea, pa, pb, au);
+            pa_prev = pa;
+            pb_prev = pb;
+            pa = pa_next;
+            pb = pb_next;
+        }
+    }
+}
+
+}  // namespace lg

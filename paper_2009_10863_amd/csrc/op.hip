@@ -2,6 +2,7 @@
 // coefficients, reciprocal diagonal) and y = A x (16 bytes per unknown).
 #include "common.h"
 #include "launch.h"
+#include "march.h"
 
 namespace lg {
 
@@ -89,8 +90,20 @@ __global__ __launch_bounds__(kBlock) void op_apply_kernel(Grid g, const double *
     }
 }
 
+__global__ __launch_bounds__(kBlock) void op_apply_march_kernel(Grid g, March m, const double *__restrict__ x,
+                                                                double *__restrict__ y) {
+    march_sweep(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &, const R2 &, const R4 &au) {
+        store4<GUESS_F64>(y, c, toV(au));
+    });
+}
+
 template <bool VAR>
 static void op_apply_v(const Grid &g, const double *x, double *y, hipStream_t s) {
+    if (!VAR && march_ok(g) && march_enabled()) {
+        const March m = make_march(g);
+        op_apply_march_kernel<<<march_grid(m), kBlock, 0, s>>>(g, m, x, y);
+        return;
+    }
     const int grid = stream_grid(nchunks(g.n), reduce_blocks());
     if (g.aligned) op_apply_kernel<VAR, true><<<grid, kBlock, 0, s>>>(g, x, y);
     else op_apply_kernel<VAR, false><<<grid, kBlock, 0, s>>>(g, x, y);

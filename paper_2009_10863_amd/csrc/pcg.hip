@@ -11,6 +11,7 @@
 // measured 6 % faster per iteration than the default schedule at 256^3.
 #include "common.h"
 #include "launch.h"
+#include "march.h"
 
 namespace lg {
 
@@ -206,62 +207,8 @@ LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, double *__restrict__ x, const double 
 }
 
 // ------------------------------------------------------------------ z-marching pcg_a
-// Same arithmetic as pcg_a_kernel, different traversal (constant
-// coefficient; every z-plane a whole number of 4-tile groups).  A wave owns
-// one 256-element tile of a z-plane and sweeps it through a range of
-// planes, keeping the search direction of planes z-1, z, z+1 in registers:
-// per step it loads r and p_old once for plane z+1 and for the rows y-1,
-// y+1, and takes the x-neighbours from the adjacent lanes (the tile's first
-// and last element from one extra load when the tile does not start or end
-// a grid row).  The 7-point values, their order and rounding are those of
-// the chunk form, so p and q are bit-identical to it.
-struct March {
-    int tp;      // 256-element tiles per z-plane
-    int zlen;    // planes per work item
-    int items;   // tp * number of plane ranges
-};
-
-static bool march_ok(const Grid &g) {
-    return !g.kx && g.aligned && g.nxy % 256 == 0 && (g.nxy / 256) % kWaves == 0;
-}
-
-static March make_march(const Grid &g) {
-    March m;
-    m.tp = (int)(g.nxy / 256);
-    // about 1024 workgroups of kWaves items each
-    int nr = (1024 * kWaves) / m.tp;
-    nr = nr < 1 ? 1 : (nr > g.nz ? g.nz : nr);
-    m.zlen = (g.nz + nr - 1) / nr;
-    nr = (g.nz + m.zlen - 1) / m.zlen;
-    m.items = m.tp * nr;
-    return m;
-}
-
-static int march_grid(const March &m) {
-    const int wg = (m.items + kWaves - 1) / kWaves;
-    return wg < kMaxPartialBlocks ? wg : kMaxPartialBlocks;
-}
-
-__device__ __forceinline__ R2 sel2(bool keep, const R2 &v) {
-    return R2{{keep ? v.v[0] : 0.0, keep ? v.v[1] : 0.0}};
-}
-
-// q at one element: fixed order west, east, south, north, bottom, top.
-__device__ __forceinline__ double q_const(const Grid &g, double uc, double w, double e, double s_, double n,
-                                          double b, double t) {
-#pragma clang fp contract(off)
-    double s = 6.0 * uc;
-    s = s - w;
-    s = s - e;
-    s = s - s_;
-    s = s - n;
-    s = s - b;
-    s = s - t;
-    const double a = g.c * s;
-    const double bb = g.shift * uc;
-    return a + bb;
-}
-
+// Same arithmetic as pcg_a_kernel in the traversal of march.h (constant
+// coefficient): p and q are bit-identical to the chunk form.
 LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, double *__restrict__ x, const double *__restrict__ r,
                                          const double *__restrict__ pold, double *__restrict__ pnew,
                                          double *__restrict__ q, const double *part_b, int nb_b, double *part_a,
@@ -277,76 +224,46 @@ LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, double *__restrict__ x
     }
     const bool first = k == 1;
     const PNext<false> pn{r, pold, nullptr, g.dinv_const, beta, first};
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // consecutive logical workgroups (neighbouring tiles) on one XCD
-    const int nwg = gridDim.x;
-    const int lb = nwg % kXcds == 0 ? (int)(blockIdx.x % kXcds) * (nwg / kXcds) + (int)(blockIdx.x / kXcds)
-                                    : (int)blockIdx.x;
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
-    const int64_t nxy = g.nxy;
     double acc[1] = {0.0};
-    for (int item = lb * kWaves + wave; item < m.items; item += nwg * kWaves) {
-        const int tau = item % m.tp, zr = item / m.tp;
-        const int z0 = zr * m.zlen;
-        const int z1 = z0 + m.zlen < nz ? z0 + m.zlen : nz;
-        const int64_t offa = (int64_t)tau * 256 + 2 * lane, offb = offa + 128;
-        const uint32_t ja = fdiv(g.fnx, (uint32_t)offa), jb = fdiv(g.fnx, (uint32_t)offb);
-        const int ia = (int)((uint32_t)offa - ja * (uint32_t)nx), ib = (int)((uint32_t)offb - jb * (uint32_t)nx);
-        const bool hwa = ia > 0, hea = ia + 2 < nx, hwb = ib > 0, heb = ib + 2 < nx;
-        const bool hsa = ja > 0, hna = (int)ja < ny - 1, hsb = jb > 0, hnb = (int)jb < ny - 1;
-        // plane z0 - 1 (bottom neighbours of the first plane) and plane z0
-        int64_t ea = (int64_t)z0 * nxy + offa;
-        const int64_t eprev = z0 > 0 ? ea - nxy : ea;
-        R2 pa_prev = sel2(z0 > 0, pn.two(eprev)), pb_prev = sel2(z0 > 0, pn.two(eprev + 128));
-        R2 pa = pn.two(ea), pb = pn.two(ea + 128);
-        for (int z = z0; z < z1; ++z, ea += nxy) {
-            const bool ht = z + 1 < nz;
-            const int64_t enext = ht ? ea + nxy : ea;
-            const R2 pa_next = sel2(ht, pn.two(enext)), pb_next = sel2(ht, pn.two(enext + 128));
-            const R2 sa = sel2(hsa, pn.two(hsa ? ea - nx : ea)), na = sel2(hna, pn.two(hna ? ea + nx : ea));
-            const R2 sb = sel2(hsb, pn.two(hsb ? ea + 128 - nx : ea + 128));
-            const R2 nb = sel2(hnb, pn.two(hnb ? ea + 128 + nx : ea + 128));
-            // x-neighbours across lanes; the tile's outer neighbours by load
-            double ew = 0.0, ee = 0.0;
-            if (lane == 0 && hwa) ew = pn(ea - 1);
-            if (lane == 63 && heb) ee = pn(ea + 256 - 2 * 63);
-            const double wa_ = __shfl(pa.v[1], (lane + 63) & 63, 64);
-            const double wb_ = __shfl(pb.v[1], (lane + 63) & 63, 64);
-            const double ea_ = __shfl(pa.v[0], (lane + 1) & 63, 64);
-            const double eb_ = __shfl(pb.v[0], (lane + 1) & 63, 64);
-            const double wa = hwa ? (lane > 0 ? wa_ : ew) : 0.0;
-            const double wb = hwb ? (lane > 0 ? wb_ : wa_) : 0.0;
-            const double eaa = hea ? (lane < 63 ? ea_ : eb_) : 0.0;
-            const double ebb = heb ? (lane < 63 ? eb_ : ee) : 0.0;
-            R4 qv;
-            qv.v[0] = q_const(g, pa.v[0], wa, pa.v[1], sa.v[0], na.v[0], pa_prev.v[0], pa_next.v[0]);
-            qv.v[1] = q_const(g, pa.v[1], pa.v[0], eaa, sa.v[1], na.v[1], pa_prev.v[1], pa_next.v[1]);
-            qv.v[2] = q_const(g, pb.v[0], wb, pb.v[1], sb.v[0], nb.v[0], pb_prev.v[0], pb_next.v[0]);
-            qv.v[3] = q_const(g, pb.v[1], pb.v[0], ebb, sb.v[1], nb.v[1], pb_prev.v[1], pb_next.v[1]);
-            if (!first) {
-                // deferred x += alpha_{k-1} p_{k-1} on this plane's pairs
-                const R2 xa = ld2(x, ea), xb = ld2(x, ea + 128);
-                const R2 oa = ld2(pold, ea), ob = ld2(pold, ea + 128);
-                __builtin_nontemporal_store(d2{__builtin_fma(alpha, oa.v[0], xa.v[0]), __builtin_fma(alpha, oa.v[1], xa.v[1])},
-                                            reinterpret_cast<d2 *>(x + ea));
-                __builtin_nontemporal_store(d2{__builtin_fma(alpha, ob.v[0], xb.v[0]), __builtin_fma(alpha, ob.v[1], xb.v[1])},
-                                            reinterpret_cast<d2 *>(x + ea + 128));
-            }
-            __builtin_nontemporal_store(d2{pa.v[0], pa.v[1]}, reinterpret_cast<d2 *>(pnew + ea));
-            __builtin_nontemporal_store(d2{pb.v[0], pb.v[1]}, reinterpret_cast<d2 *>(pnew + ea + 128));
-            __builtin_nontemporal_store(d2{qv.v[0], qv.v[1]}, reinterpret_cast<d2 *>(q + ea));
-            __builtin_nontemporal_store(d2{qv.v[2], qv.v[3]}, reinterpret_cast<d2 *>(q + ea + 128));
-            acc[0] = __builtin_fma(pa.v[0], qv.v[0], acc[0]);
-            acc[0] = __builtin_fma(pa.v[1], qv.v[1], acc[0]);
-            acc[0] = __builtin_fma(pb.v[0], qv.v[2], acc[0]);
-            acc[0] = __builtin_fma(pb.v[1], qv.v[3], acc[0]);
-            pa_prev = pa;
-            pb_prev = pb;
-            pa = pa_next;
-            pb = pb_next;
+    march_sweep(g, m, pn, [&](int64_t c, int64_t e, const R2 &pa, const R2 &pb, const R4 &qv) {
+        if (!first) {
+            // deferred x += alpha_{k-1} p_{k-1} on this chunk
+            V4 xv = load4<GUESS_F64>(x, c);
+            const V4 ov = load4<GUESS_F64>(pold, c);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xv.v[i] = __builtin_fma(alpha, ov.v[i], xv.v[i]);
+            store4<GUESS_F64>(x, c, xv);
         }
-    }
+        store4<GUESS_F64>(pnew, c, V4{{pa.v[0], pa.v[1], pb.v[0], pb.v[1]}});
+        store4<GUESS_F64>(q, c, toV(qv));
+        acc[0] = __builtin_fma(pa.v[0], qv.v[0], acc[0]);
+        acc[0] = __builtin_fma(pa.v[1], qv.v[1], acc[0]);
+        acc[0] = __builtin_fma(pb.v[0], qv.v[2], acc[0]);
+        acc[0] = __builtin_fma(pb.v[1], qv.v[3], acc[0]);
+        (void)e;
+    });
     block_partials<1>(acc, part_a, lds);
+}
+
+// r = b - A x in the traversal of march.h; rows (r^T r, r^T D^{-1} r, b^T b).
+LG_REDUCE_KERNEL void pcg_init_march_kernel(Grid g, March m, const double *__restrict__ b,
+                                            const double *__restrict__ x, double *__restrict__ r, double *part) {
+    __shared__ double lds[kLdsDoubles];
+    double acc[3] = {0.0, 0.0, 0.0};
+    const double dv = g.dinv_const;
+    march_sweep(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &, const R2 &, const R4 &ax) {
+        const V4 bv = load4<GUESS_F64>(b, c);
+        V4 rv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            rv.v[e] = bv.v[e] - ax.v[e];
+            acc[0] = __builtin_fma(rv.v[e], rv.v[e], acc[0]);
+            acc[1] = __builtin_fma(rv.v[e], dv * rv.v[e], acc[1]);
+            acc[2] = __builtin_fma(bv.v[e], bv.v[e], acc[2]);
+        }
+        store4<GUESS_F64>(r, c, rv);
+    });
+    block_partials<3>(acc, part, lds);
 }
 
 template <bool VAR>
@@ -394,6 +311,11 @@ LG_REDUCE_KERNEL void pcg_b_kernel(Grid g, double *__restrict__ r, const double 
 
 int launch_pcg_init(const Grid &g, const double *b, const double *x, double *r, double *part_b, hipStream_t s) {
     const int gr = pcg_grid(g);
+    if (march_ok(g) && march_enabled()) {
+        // same number of partial rows as the chunk form (the consumers expect gr)
+        pcg_init_march_kernel<<<gr, kBlock, 0, s>>>(g, make_march(g), b, x, r, part_b);
+        return GUESS_OK;
+    }
     if (g.kx) {
         if (g.aligned) pcg_init_kernel<true, true><<<gr, kBlock, 0, s>>>(g, b, x, r, part_b);
         else pcg_init_kernel<true, false><<<gr, kBlock, 0, s>>>(g, b, x, r, part_b);

@@ -47,6 +47,7 @@
 
 #include "common.h"
 #include "launch.h"
+#include "march.h"
 
 namespace lg {
 
@@ -234,6 +235,51 @@ LG_REDUCE_KERNEL void proj_apply_kernel(ProjArgs a, Grid g, const double *__rest
 #pragma unroll
             for (int j = 0; j < D; ++j) acc[j] = __builtin_fma(load1<DT>(colp<DT>(C, a.ld, j), i), wv, acc[j]);
         }
+        block_partials<ND>(acc, a.part, lds);
+    });
+}
+
+// proj_apply in the traversal of march.h (constant coefficient, library
+// operator, grids it applies to): same per-chunk work, bit-identical w.
+template <int DT, int VF>
+LG_REDUCE_KERNEL void proj_apply_march_kernel(ProjArgs a, Grid g, March m, const double *__restrict__ x) {
+    __shared__ double lds[kLdsDoubles];
+    constexpr bool L2 = (VF & VF_L2) != 0;
+    const int d = a.st->d;
+    if (proj_restart<VF>(d, a.M)) {
+        double acc[1] = {0.0};
+        march_sweep(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &pa, const R2 &pb, const R4 &au) {
+            const V4 xv{{pa.v[0], pa.v[1], pb.v[0], pb.v[1]}};
+            const V4 wv{{au.v[0], au.v[1], au.v[2], au.v[3]}};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[0]);
+            store4<DT>(a.Xw, c, xv);
+            store4<DT>(a.Bw, c, wv);
+        });
+        block_partials<1>(acc, a.part, lds);
+        return;
+    }
+    const void *C = dot_cols<VF>(a);
+    dispatch_d<1, gs_max<VF>()>(d, [&](auto Dc) {
+        constexpr int D = decltype(Dc)::value;
+        constexpr int ND = D + 1;
+        double acc[ND];
+#pragma unroll
+        for (int j = 0; j < ND; ++j) acc[j] = 0.0;
+        march_sweep(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &pa, const R2 &pb, const R4 &au) {
+            V4 xc[D];
+#pragma unroll
+            for (int j = 0; j < D; ++j) xc[j] = load4<DT>(colp<DT>(C, a.ld, j), c);
+            const V4 xv{{pa.v[0], pa.v[1], pb.v[0], pb.v[1]}};
+            const V4 wv{{au.v[0], au.v[1], au.v[2], au.v[3]}};
+            store4<GUESS_F64>(a.w, c, wv);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[D] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[D]);
+#pragma unroll
+            for (int j = 0; j < D; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[j] = __builtin_fma(xc[j].v[e], wv.v[e], acc[j]);
+        });
         block_partials<ND>(acc, a.part, lds);
     });
 }
@@ -658,7 +704,12 @@ void proj_update_dt(const ProjBufs &p, const Grid *g, const double *x, const dou
     const ProjArgs a = make_args(p);
     const int gr = stream_grid(nchunks(a.N), reduce_blocks());
     const Grid gg = g ? *g : Grid{};
-    if (Ax) {
+    int ga = gr;   // partial rows written by the apply kernel
+    if (!Ax && march_ok(*g) && march_enabled()) {
+        const March m = make_march(*g);
+        ga = march_grid(m);
+        klaunch(ev, 0, proj_apply_march_kernel<DT, VF>, ga, kBlock, s, a, gg, m, x);
+    } else if (Ax) {
         klaunch(ev, 0, proj_apply_kernel<DT, VF, false, true, true>, gr, kBlock, s, a, gg, x, Ax);
     } else if (g->kx) {
         if (g->aligned) klaunch(ev, 0, proj_apply_kernel<DT, VF, true, false, true>, gr, kBlock, s, a, gg, x, Ax);
@@ -667,7 +718,7 @@ void proj_update_dt(const ProjBufs &p, const Grid *g, const double *x, const dou
         if (g->aligned) klaunch(ev, 0, proj_apply_kernel<DT, VF, false, false, true>, gr, kBlock, s, a, gg, x, Ax);
         else klaunch(ev, 0, proj_apply_kernel<DT, VF, false, false, false>, gr, kBlock, s, a, gg, x, Ax);
     }
-    klaunch(ev, 1, proj_fin_kernel<FIN_APPLY, VF>, 1, kBlock, s, a, gr);
+    klaunch(ev, 1, proj_fin_kernel<FIN_APPLY, VF>, 1, kBlock, s, a, ga);
     const double *w = Ax ? Ax : a.w;
     klaunch(ev, 2, proj_reorth_kernel<DT, VF>, gr, kBlock, s, a, w);
     klaunch(ev, 3, proj_fin_kernel<FIN_REORTH, VF>, 1, kBlock, s, a, gr);
