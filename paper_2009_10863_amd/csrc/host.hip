@@ -486,6 +486,7 @@ static int proj_upload_state(guess_ctx *g) {
     lg::ProjState s{};
     s.M = g->M;
     s.eps_rel = g->eps_rel;
+    s.pow2 = 1.0;
     *g->host_st = s;
     LG_HIP(hipMemcpyAsync(g->st, g->host_st, sizeof s, hipMemcpyHostToDevice, g->stream));
     LG_HIP(hipStreamSynchronize(g->stream));

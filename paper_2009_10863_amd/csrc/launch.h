@@ -46,6 +46,7 @@ struct ProjState {
     int pad;
     double eps_rel;
     double nu0sq, nusq, nu0, nu;
+    double pow2;            // power of two the current update's new pair is stored multiplied by
     double scale[GUESS_MAX_M];   // column j of X (and B) = scale[j] * stored column j
     double gamma[GUESS_MAX_M];   // guess: x0 = sum_j gamma[j] * stored X_j
     double c[GUESS_MAX_M];       // update: Gram-Schmidt coefficients (true units)

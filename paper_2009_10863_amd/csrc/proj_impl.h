@@ -284,21 +284,31 @@ LG_REDUCE_KERNEL void proj_apply_march_kernel(ProjArgs a, Grid g, March m, const
     });
 }
 
+// FP16 storage has a narrow range, so each new FP16 column is stored
+// multiplied by a power of two chosen from its norm after the first
+// Gram-Schmidt pass (computed here as one more partial sum; the A-form
+// also reads x for it).  Wider formats store the column as it is.
+template <int DT>
+constexpr bool scaled_store() {
+    return DT == GUESS_F16;
+}
+
 template <int DT, int VF>
-LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ w) {
+LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ x, const double *__restrict__ w) {
     __shared__ double lds[kLdsDoubles];
     constexpr bool L2 = (VF & VF_L2) != 0;
+    constexpr bool EST = scaled_store<DT>();
     if (a.st->mode != 0) return;
     const int d = a.st->d;
     const int64_t nc = nchunks(a.N), stride = (int64_t)gridDim.x * kBlock;
     dispatch_d<1, gs_max<VF>()>(d, [&](auto Dc) {
         constexpr int D = decltype(Dc)::value;
-        double cs[D], acc[D];
+        constexpr int ND = EST ? D + 1 : D;
+        double cs[D], acc[ND];
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            cs[j] = a.st->cs[j];
-            acc[j] = 0.0;
-        }
+        for (int j = 0; j < D; ++j) cs[j] = a.st->cs[j];
+#pragma unroll
+        for (int j = 0; j < ND; ++j) acc[j] = 0.0;
         for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
             V4 bc[D], xc[L2 ? 1 : D];
 #pragma unroll
@@ -317,17 +327,35 @@ LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ 
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
                     acc[j] = __builtin_fma(L2 ? bc[j].v[e] : xc[L2 ? 0 : j].v[e], wv.v[e], acc[j]);
+            if constexpr (EST) {
+                if constexpr (L2) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[D] = __builtin_fma(wv.v[e], wv.v[e], acc[D]);
+                } else {
+                    V4 xv = load4<GUESS_F64>(x, c);
+#pragma unroll
+                    for (int j = 0; j < D; ++j)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) xv.v[e] = __builtin_fma(-cs[j], xc[j].v[e], xv.v[e]);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[D] = __builtin_fma(xv.v[e], wv.v[e], acc[D]);
+                }
+            }
         }
         if (blockIdx.x == 0 && threadIdx.x < tail_count(a.N)) {
             const int64_t i = tail_start(a.N) + threadIdx.x;
-            double wv = w[i];
+            double wv = w[i], xv = x[i];
 #pragma unroll
-            for (int j = 0; j < D; ++j) wv = __builtin_fma(-cs[j], load1<DT>(colp<DT>(a.B, a.ld, j), i), wv);
+            for (int j = 0; j < D; ++j) {
+                wv = __builtin_fma(-cs[j], load1<DT>(colp<DT>(a.B, a.ld, j), i), wv);
+                if constexpr (EST && !L2) xv = __builtin_fma(-cs[j], load1<DT>(colp<DT>(a.X, a.ld, j), i), xv);
+            }
 #pragma unroll
             for (int j = 0; j < D; ++j)
                 acc[j] = __builtin_fma(load1<DT>(colp<DT>(L2 ? a.B : a.X, a.ld, j), i), wv, acc[j]);
+            if constexpr (EST) acc[D] = __builtin_fma(L2 ? wv : xv, wv, acc[D]);
         }
-        block_partials<D>(acc, a.part, lds);
+        block_partials<ND>(acc, a.part, lds);
     });
 }
 
@@ -337,7 +365,7 @@ LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ 
 // new_i = a t_i + b S_{i+1}, t_{i+1} = e t_i + f S_{i+1}, t_0 = S_0.
 template <int DT, int D>
 __device__ __forceinline__ void rotate_chunk(const void *S, void *Sw, int64_t ld, int64_t c, const double (&cs)[D],
-                                             const double (&rot)[D - 1][4], V4 &v) {
+                                             const double (&rot)[D - 1][4], double pw, V4 &v) {
     V4 col[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) col[j] = load4<DT>(colp<DT>(S, ld, j), c);
@@ -356,12 +384,14 @@ __device__ __forceinline__ void rotate_chunk(const void *S, void *Sw, int64_t ld
         }
         store4<DT>(colw<DT>(Sw, ld, i), c, nw);
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v.v[e] *= pw;
     store4<DT>(colw<DT>(Sw, ld, D - 1), c, v);
 }
 
 template <int DT, int D>
 __device__ __forceinline__ double rotate_one(const void *S, void *Sw, int64_t ld, int64_t i, const double (&cs)[D],
-                                             const double (&rot)[D - 1][4], double v) {
+                                             const double (&rot)[D - 1][4], double pw, double v) {
     double col[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) col[j] = load1<DT>(colp<DT>(S, ld, j), i);
@@ -374,6 +404,7 @@ __device__ __forceinline__ double rotate_one(const void *S, void *Sw, int64_t ld
         t = __builtin_fma(rot[q][3], col[q + 1], rot[q][2] * t);
         store1<DT>(colw<DT>(Sw, ld, q), i, nw);
     }
+    v *= pw;
     store1<DT>(colw<DT>(Sw, ld, D - 1), i, v);
     return v;
 }
@@ -397,19 +428,20 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
                 for (int i = 0; i < D - 1; ++i)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) rot[i][q] = a.st->rot[i][q];
+                const double pw = scaled_store<DT>() ? a.st->pow2 : 1.0;
                 double acc[1] = {0.0};
                 for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
                     V4 xv = load4<GUESS_F64>(x, c);
                     V4 wv = load4<GUESS_F64>(w, c);
-                    rotate_chunk<DT, D>(a.X, a.Xw, a.ld, c, cs, rot, xv);
-                    rotate_chunk<DT, D>(a.B, a.Bw, a.ld, c, cs, rot, wv);
+                    rotate_chunk<DT, D>(a.X, a.Xw, a.ld, c, cs, rot, pw, xv);
+                    rotate_chunk<DT, D>(a.B, a.Bw, a.ld, c, cs, rot, pw, wv);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[0]);
                 }
                 if (blockIdx.x == 0 && threadIdx.x < tail_count(a.N)) {
                     const int64_t i = tail_start(a.N) + threadIdx.x;
-                    const double xv = rotate_one<DT, D>(a.X, a.Xw, a.ld, i, cs, rot, x[i]);
-                    const double wv = rotate_one<DT, D>(a.B, a.Bw, a.ld, i, cs, rot, w[i]);
+                    const double xv = rotate_one<DT, D>(a.X, a.Xw, a.ld, i, cs, rot, pw, x[i]);
+                    const double wv = rotate_one<DT, D>(a.B, a.Bw, a.ld, i, cs, rot, pw, w[i]);
                     acc[0] = __builtin_fma(L2 ? wv : xv, wv, acc[0]);
                 }
                 block_partials<1>(acc, a.part, lds);
@@ -424,6 +456,7 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
         for (int j = 0; j < D; ++j) cs[j] = a.st->cs[j];
         void *Xd = colw<DT>(a.Xw, a.ld, D);
         void *Bd = colw<DT>(a.Bw, a.ld, D);
+        const double pw = scaled_store<DT>() ? a.st->pow2 : 1.0;
         double acc[1] = {0.0};
         for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
             V4 xc[D], bc[D];
@@ -441,7 +474,11 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
                     wv.v[e] = __builtin_fma(-cs[j], bc[j].v[e], wv.v[e]);
                 }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[0]);
+            for (int e = 0; e < 4; ++e) {
+                xv.v[e] *= pw;
+                wv.v[e] *= pw;
+                acc[0] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[0]);
+            }
             store4<DT>(Xd, c, xv);
             store4<DT>(Bd, c, wv);
         }
@@ -453,6 +490,8 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
                 xv = __builtin_fma(-cs[j], load1<DT>(colp<DT>(a.X, a.ld, j), i), xv);
                 wv = __builtin_fma(-cs[j], load1<DT>(colp<DT>(a.B, a.ld, j), i), wv);
             }
+            xv *= pw;
+            wv *= pw;
             acc[0] = __builtin_fma(L2 ? wv : xv, wv, acc[0]);
             store1<DT>(Xd, i, xv);
             store1<DT>(Bd, i, wv);
@@ -539,7 +578,7 @@ __device__ __forceinline__ void qr_drop_plan(ProjState *st, int M) {
     }
 }
 
-template <int KIND, int VF>
+template <int KIND, int VF, int DT>
 __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
     __shared__ double lds[kLdsDoubles];
     ProjState *st = a.st;
@@ -619,8 +658,9 @@ __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
         const bool drop = (VF & VF_QR) != 0 && st->drop != 0;
         dispatch_d<1, gs_max<VF>()>(d, [&](auto Dc) {
             constexpr int D = decltype(Dc)::value;
-            double tot[D];
-            final_sums<D>(a.part, nb, tot, lds);
+            constexpr int ND = scaled_store<DT>() ? D + 1 : D;
+            double tot[ND];
+            final_sums<ND>(a.part, nb, tot, lds);
             if (drop) {
                 if constexpr (D >= 2) {
                     if (threadIdx.x == 0) {
@@ -643,6 +683,21 @@ __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
                 st->c[threadIdx.x] = cj;
                 st->cs[threadIdx.x] = cj * sc;
             }
+            if constexpr (scaled_store<DT>()) {
+                if (threadIdx.x == 0) {
+                    // store the new pair multiplied by the power of two that brings its
+                    // norm after the first pass, nu1, back to the raw solution's nu0
+                    // (exact): the stored values stay in the range of the raw solutions
+                    const double nu0 = st->nu0, nu1 = sqrt(tot[D]);
+                    double pw = 1.0;
+                    if (isfinite(nu0) && nu0 > 0.0 && isfinite(nu1) && nu1 > 0.0) {
+                        int ex = ilogb(nu0) - ilogb(nu1);
+                        ex = ex < 0 ? 0 : (ex > 60 ? 60 : ex);
+                        pw = ldexp(1.0, ex);
+                    }
+                    st->pow2 = pw;
+                }
+            }
         });
     } else {
         if (st->mode != 0 || d < 1 || d > a.M) return;
@@ -651,18 +706,19 @@ __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
         double tot[1];
         final_sums<1>(a.part, nb, tot, lds);
         const int slot = drop ? d - 1 : d;     // the new pair's column
-        const double nu = sqrt(tot[0]);        // NaN when rounding made it negative
+        const double pw = scaled_store<DT>() ? st->pow2 : 1.0;   // the pair was stored multiplied by pw
+        const double nu = sqrt(tot[0]) / pw;   // NaN when rounding made it negative
         const bool fin = isfinite(nu);
         const bool ok = fin && nu > st->eps_rel * st->nu0;
         // new column of the factor: raw x = X c + nu x~
         if (ok && threadIdx.x < slot) st->R[threadIdx.x][slot] = st->c[threadIdx.x];
         if (threadIdx.x == 0) {
-            st->nusq = tot[0];
+            st->nusq = tot[0] / (pw * pw);
             st->nu = nu;
             st->last_accepted = ok ? 1 : 0;
             if (!fin) st->nonfinite = 1;
             if (ok) {
-                st->scale[slot] = 1.0 / nu;
+                st->scale[slot] = 1.0 / (nu * pw);
                 st->R[slot][slot] = nu;
                 st->d = slot + 1;
             } else {
@@ -694,7 +750,7 @@ void proj_form_dt(const ProjBufs &p, const double *b, double *x0, hipStream_t s,
     const ProjArgs a = make_args(p);
     const int gr = stream_grid(nchunks(a.N), reduce_blocks());
     klaunch(ev, 0, proj_dots_kernel<DT, VF>, gr, kBlock, s, a, b);
-    klaunch(ev, 1, proj_fin_kernel<FIN_DOTS, VF>, 1, kBlock, s, a, gr);
+    klaunch(ev, 1, proj_fin_kernel<FIN_DOTS, VF, DT>, 1, kBlock, s, a, gr);
     klaunch(ev, 2, proj_combine_kernel<DT>, stream_grid(nchunks(a.N), grid_cap()), kBlock, s, a, x0);
 }
 
@@ -718,12 +774,12 @@ void proj_update_dt(const ProjBufs &p, const Grid *g, const double *x, const dou
         if (g->aligned) klaunch(ev, 0, proj_apply_kernel<DT, VF, false, false, true>, gr, kBlock, s, a, gg, x, Ax);
         else klaunch(ev, 0, proj_apply_kernel<DT, VF, false, false, false>, gr, kBlock, s, a, gg, x, Ax);
     }
-    klaunch(ev, 1, proj_fin_kernel<FIN_APPLY, VF>, 1, kBlock, s, a, ga);
+    klaunch(ev, 1, proj_fin_kernel<FIN_APPLY, VF, DT>, 1, kBlock, s, a, ga);
     const double *w = Ax ? Ax : a.w;
-    klaunch(ev, 2, proj_reorth_kernel<DT, VF>, gr, kBlock, s, a, w);
-    klaunch(ev, 3, proj_fin_kernel<FIN_REORTH, VF>, 1, kBlock, s, a, gr);
+    klaunch(ev, 2, proj_reorth_kernel<DT, VF>, gr, kBlock, s, a, x, w);
+    klaunch(ev, 3, proj_fin_kernel<FIN_REORTH, VF, DT>, 1, kBlock, s, a, gr);
     klaunch(ev, 4, proj_gs_write_kernel<DT, VF>, gr, kBlock, s, a, x, w);
-    klaunch(ev, 5, proj_fin_kernel<FIN_GS, VF>, 1, kBlock, s, a, gr);
+    klaunch(ev, 5, proj_fin_kernel<FIN_GS, VF, DT>, 1, kBlock, s, a, gr);
 }
 
 }  // namespace lg
