@@ -72,8 +72,13 @@ def face_coeffs(kappa_nodal: np.ndarray, n: int):
     in (z, y, x) order: ``kx[l, j, f]`` is the face between padded nodes
     f and f+1 along x at interior row (j, l); likewise for y and z.
     """
-    m = n + 2
-    K = np.asarray(kappa_nodal, dtype=np.float64).reshape(m, m, m)
+    return face_coeffs_box(kappa_nodal, (n, n, n))
+
+
+def face_coeffs_box(kappa_nodal: np.ndarray, shape):
+    """The same on an nx x ny x nz box: kappa on (nz+2, ny+2, nx+2) nodes, x fastest."""
+    nx, ny, nz = shape
+    K = np.asarray(kappa_nodal, dtype=np.float64).reshape(nz + 2, ny + 2, nx + 2)
     I = slice(1, -1)
     kx = harmonic(K[I, I, :-1], K[I, I, 1:])
     ky = harmonic(K[I, :-1, I], K[I, 1:, I])
@@ -84,8 +89,15 @@ def face_coeffs(kappa_nodal: np.ndarray, n: int):
 def apply_var(u: np.ndarray, n: int, faces, shift: float = 10.0, c: float = None) -> np.ndarray:
     """y = A u for -div(kappa grad u) + shift u (harmonic-mean faces)."""
     c = inv_h2(n) if c is None else c
+    return apply_var_box(u, (n, n, n), faces, c, shift)
+
+
+def apply_var_box(u: np.ndarray, shape, faces, c: float, shift: float = 10.0) -> np.ndarray:
+    """The same on an nx x ny x nz box (faces from face_coeffs_box)."""
+    nx, ny, nz = shape
     kx, ky, kz = faces
-    P = _pad(u, n)
+    P = np.zeros((nz + 2, ny + 2, nx + 2), dtype=np.float64)
+    P[1:-1, 1:-1, 1:-1] = np.asarray(u, dtype=np.float64).reshape(nz, ny, nx)
     U = P[1:-1, 1:-1, 1:-1]
     s = kx[:, :, :-1] * (U - P[1:-1, 1:-1, :-2])            # west
     s = s + kx[:, :, 1:] * (U - P[1:-1, 1:-1, 2:])          # east

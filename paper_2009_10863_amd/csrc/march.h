@@ -1,4 +1,4 @@
-// z-marching traversal for the constant-coefficient 7-point stencil.
+// z-marching traversal for the 7-point stencils.
 //
 // Applies where every z-plane is a whole number of 4-tile groups (nx even,
 // nx*ny a multiple of 1024).  A wave owns one 256-element tile of a z-plane
@@ -29,7 +29,7 @@ struct March {
 };
 
 inline bool march_ok(const Grid &g) {
-    return !g.kx && g.aligned && g.nxy % 256 == 0 && (g.nxy / 256) % kWaves == 0;
+    return g.aligned && g.nxy % 256 == 0 && (g.nxy / 256) % kWaves == 0;
 }
 
 inline March make_march(const Grid &g) {
@@ -69,11 +69,30 @@ __device__ __forceinline__ double q_const(const Grid &g, double uc, double w, do
     return a + bb;
 }
 
+// (A u) at one element, variable coefficient: faces west, east, south,
+// north, bottom, top in this order, then c*s + shift*u.
+__device__ __forceinline__ double q_var(const Grid &g, double uc, double kw, double w, double ke, double e,
+                                        double ks, double s_, double kn, double n, double kb, double b, double kt,
+                                        double t) {
+#pragma clang fp contract(off)
+    double s = kw * (uc - w);
+    s = s + ke * (uc - e);
+    s = s + ks * (uc - s_);
+    s = s + kn * (uc - n);
+    s = s + kb * (uc - b);
+    s = s + kt * (uc - t);
+    const double a = g.c * s;
+    const double bb = g.shift * uc;
+    return a + bb;
+}
+
 // Sweep the wave's work items.  U: operand access (u(q), u.two(q) as in
 // stencil.h).  f(c, e, ua, ub, au) is called once per chunk with its chunk
 // index c (as in common.h), the flat index e of its first pair, the centre
-// values of both pairs and A u at the chunk's four elements.
-template <class U, class F>
+// values of both pairs and A u at the chunk's four elements.  VAR: variable
+// coefficient (face arrays of the Grid; the z-faces shared by consecutive
+// planes are loaded once).
+template <bool VAR, class U, class F>
 __device__ __forceinline__ void march_sweep(const Grid &g, const March &m, const U &u, F &&f) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwg = gridDim.x;
@@ -95,6 +114,12 @@ __device__ __forceinline__ void march_sweep(const Grid &g, const March &m, const
         const int64_t eprev = z0 > 0 ? ea - nxy : ea;
         R2 pa_prev = sel2(z0 > 0, u.two(eprev)), pb_prev = sel2(z0 > 0, u.two(eprev + 128));
         R2 pa = u.two(ea), pb = u.two(ea + 128);
+        // bottom z-faces of plane z0 (face index f = z: kz[(f*ny + j)*nx + i] = kz[e])
+        R2 kba{{0.0, 0.0}}, kbb{{0.0, 0.0}};
+        if constexpr (VAR) {
+            kba = ld2(g.kz, ea);
+            kbb = ld2(g.kz, ea + 128);
+        }
         for (int z = z0; z < z1; ++z, ea += nxy, c += (int64_t)m.tp * 64) {
             const bool ht = z + 1 < nz;
             const int64_t enext = ht ? ea + nxy : ea;
@@ -115,10 +140,33 @@ __device__ __forceinline__ void march_sweep(const Grid &g, const March &m, const
             const double eaa = hea ? (lane < 63 ? ea_ : eb_) : 0.0;
             const double ebb = heb ? (lane < 63 ? eb_ : ee) : 0.0;
             R4 au;
-            au.v[0] = q_const(g, pa.v[0], wa, pa.v[1], sa.v[0], na.v[0], pa_prev.v[0], pa_next.v[0]);
-            au.v[1] = q_const(g, pa.v[1], pa.v[0], eaa, sa.v[1], na.v[1], pa_prev.v[1], pa_next.v[1]);
-            au.v[2] = q_const(g, pb.v[0], wb, pb.v[1], sb.v[0], nb.v[0], pb_prev.v[0], pb_next.v[0]);
-            au.v[3] = q_const(g, pb.v[1], pb.v[0], ebb, sb.v[1], nb.v[1], pb_prev.v[1], pb_next.v[1]);
+            if constexpr (!VAR) {
+                au.v[0] = q_const(g, pa.v[0], wa, pa.v[1], sa.v[0], na.v[0], pa_prev.v[0], pa_next.v[0]);
+                au.v[1] = q_const(g, pa.v[1], pa.v[0], eaa, sa.v[1], na.v[1], pa_prev.v[1], pa_next.v[1]);
+                au.v[2] = q_const(g, pb.v[0], wb, pb.v[1], sb.v[0], nb.v[0], pb_prev.v[0], pb_next.v[0]);
+                au.v[3] = q_const(g, pb.v[1], pb.v[0], ebb, sb.v[1], nb.v[1], pb_prev.v[1], pb_next.v[1]);
+            } else {
+                // x-faces of each pair's row (nx+1 per row), y-faces south / north, z-faces top
+                const int64_t rxa = ((int64_t)z * ny + ja) * (nx + 1) + ia;
+                const int64_t rxb = ((int64_t)z * ny + jb) * (nx + 1) + ib;
+                const int64_t rya = ((int64_t)z * (ny + 1) + ja) * nx + ia;
+                const int64_t ryb = ((int64_t)z * (ny + 1) + jb) * nx + ib;
+                const double xa0 = g.kx[rxa], xa1 = g.kx[rxa + 1], xa2 = g.kx[rxa + 2];
+                const double xb0 = g.kx[rxb], xb1 = g.kx[rxb + 1], xb2 = g.kx[rxb + 2];
+                const R2 ksa = ld2(g.ky, rya), kna = ld2(g.ky, rya + nx);
+                const R2 ksb = ld2(g.ky, ryb), knb = ld2(g.ky, ryb + nx);
+                const R2 kta = ld2(g.kz, ea + nxy), ktb = ld2(g.kz, ea + 128 + nxy);
+                au.v[0] = q_var(g, pa.v[0], xa0, wa, xa1, pa.v[1], ksa.v[0], sa.v[0], kna.v[0], na.v[0], kba.v[0],
+                                pa_prev.v[0], kta.v[0], pa_next.v[0]);
+                au.v[1] = q_var(g, pa.v[1], xa1, pa.v[0], xa2, eaa, ksa.v[1], sa.v[1], kna.v[1], na.v[1], kba.v[1],
+                                pa_prev.v[1], kta.v[1], pa_next.v[1]);
+                au.v[2] = q_var(g, pb.v[0], xb0, wb, xb1, pb.v[1], ksb.v[0], sb.v[0], knb.v[0], nb.v[0], kbb.v[0],
+                                pb_prev.v[0], ktb.v[0], pb_next.v[0]);
+                au.v[3] = q_var(g, pb.v[1], xb1, pb.v[0], xb2, ebb, ksb.v[1], sb.v[1], knb.v[1], nb.v[1], kbb.v[1],
+                                pb_prev.v[1], ktb.v[1], pb_next.v[1]);
+                kba = kta;
+                kbb = ktb;
+            }
             f(c, ea, pa, pb, au);
             pa_prev = pa;
             pb_prev = pb;

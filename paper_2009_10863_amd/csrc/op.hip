@@ -90,18 +90,19 @@ __global__ __launch_bounds__(kBlock) void op_apply_kernel(Grid g, const double *
     }
 }
 
+template <bool VAR>
 __global__ __launch_bounds__(kBlock) void op_apply_march_kernel(Grid g, March m, const double *__restrict__ x,
                                                                 double *__restrict__ y) {
-    march_sweep(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &, const R2 &, const R4 &au) {
+    march_sweep<VAR>(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &, const R2 &, const R4 &au) {
         store4<GUESS_F64>(y, c, toV(au));
     });
 }
 
 template <bool VAR>
 static void op_apply_v(const Grid &g, const double *x, double *y, hipStream_t s) {
-    if (!VAR && march_ok(g) && march_enabled()) {
+    if (march_ok(g) && march_enabled()) {
         const March m = make_march(g);
-        op_apply_march_kernel<<<march_grid(m), kBlock, 0, s>>>(g, m, x, y);
+        op_apply_march_kernel<VAR><<<march_grid(m), kBlock, 0, s>>>(g, m, x, y);
         return;
     }
     const int grid = stream_grid(nchunks(g.n), reduce_blocks());

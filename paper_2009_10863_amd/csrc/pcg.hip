@@ -209,6 +209,7 @@ LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, double *__restrict__ x, const double 
 // ------------------------------------------------------------------ z-marching pcg_a
 // Same arithmetic as pcg_a_kernel in the traversal of march.h (constant
 // coefficient): p and q are bit-identical to the chunk form.
+template <bool VAR>
 LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, double *__restrict__ x, const double *__restrict__ r,
                                          const double *__restrict__ pold, double *__restrict__ pnew,
                                          double *__restrict__ q, const double *part_b, int nb_b, double *part_a,
@@ -223,9 +224,9 @@ LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, double *__restrict__ x
         return;
     }
     const bool first = k == 1;
-    const PNext<false> pn{r, pold, nullptr, g.dinv_const, beta, first};
+    const PNext<VAR> pn{r, pold, g.dinv, g.dinv_const, beta, first};
     double acc[1] = {0.0};
-    march_sweep(g, m, pn, [&](int64_t c, int64_t e, const R2 &pa, const R2 &pb, const R4 &qv) {
+    march_sweep<VAR>(g, m, pn, [&](int64_t c, int64_t e, const R2 &pa, const R2 &pb, const R4 &qv) {
         if (!first) {
             // deferred x += alpha_{k-1} p_{k-1} on this chunk
             V4 xv = load4<GUESS_F64>(x, c);
@@ -246,19 +247,19 @@ LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, double *__restrict__ x
 }
 
 // r = b - A x in the traversal of march.h; rows (r^T r, r^T D^{-1} r, b^T b).
+template <bool VAR>
 LG_REDUCE_KERNEL void pcg_init_march_kernel(Grid g, March m, const double *__restrict__ b,
                                             const double *__restrict__ x, double *__restrict__ r, double *part) {
     __shared__ double lds[kLdsDoubles];
     double acc[3] = {0.0, 0.0, 0.0};
-    const double dv = g.dinv_const;
-    march_sweep(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &, const R2 &, const R4 &ax) {
-        const V4 bv = load4<GUESS_F64>(b, c);
+    march_sweep<VAR>(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &, const R2 &, const R4 &ax) {
+        const V4 bv = load4<GUESS_F64>(b, c), dv = dinv4<VAR>(g, c);
         V4 rv;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             rv.v[e] = bv.v[e] - ax.v[e];
             acc[0] = __builtin_fma(rv.v[e], rv.v[e], acc[0]);
-            acc[1] = __builtin_fma(rv.v[e], dv * rv.v[e], acc[1]);
+            acc[1] = __builtin_fma(rv.v[e], dv.v[e] * rv.v[e], acc[1]);
             acc[2] = __builtin_fma(bv.v[e], bv.v[e], acc[2]);
         }
         store4<GUESS_F64>(r, c, rv);
@@ -313,7 +314,8 @@ int launch_pcg_init(const Grid &g, const double *b, const double *x, double *r, 
     const int gr = pcg_grid(g);
     if (march_ok(g) && march_enabled()) {
         // same number of partial rows as the chunk form (the consumers expect gr)
-        pcg_init_march_kernel<<<gr, kBlock, 0, s>>>(g, make_march(g), b, x, r, part_b);
+        if (g.kx) pcg_init_march_kernel<true><<<gr, kBlock, 0, s>>>(g, make_march(g), b, x, r, part_b);
+        else pcg_init_march_kernel<false><<<gr, kBlock, 0, s>>>(g, make_march(g), b, x, r, part_b);
         return GUESS_OK;
     }
     if (g.kx) {
@@ -333,10 +335,10 @@ static void pcg_iter_v(const Grid &g, double *x, double *r, double *const p[2], 
     double *pnew = p[k & 1];
     const double *pold = p[(k - 1) & 1];
     int ga = gr;
-    if (!VAR && AL && march_ok(g) && march_enabled()) {
+    if (AL && march_ok(g) && march_enabled()) {
         const March m = make_march(g);
         ga = march_grid(m);
-        pcg_a_march_kernel<<<ga, kBlock, 0, s>>>(g, m, x, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
+        pcg_a_march_kernel<VAR><<<ga, kBlock, 0, s>>>(g, m, x, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
     } else {
         pcg_a_kernel<VAR, AL><<<gr, kBlock, 0, s>>>(g, x, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
     }

@@ -241,14 +241,14 @@ LG_REDUCE_KERNEL void proj_apply_kernel(ProjArgs a, Grid g, const double *__rest
 
 // proj_apply in the traversal of march.h (constant coefficient, library
 // operator, grids it applies to): same per-chunk work, bit-identical w.
-template <int DT, int VF>
+template <int DT, int VF, bool VAR>
 LG_REDUCE_KERNEL void proj_apply_march_kernel(ProjArgs a, Grid g, March m, const double *__restrict__ x) {
     __shared__ double lds[kLdsDoubles];
     constexpr bool L2 = (VF & VF_L2) != 0;
     const int d = a.st->d;
     if (proj_restart<VF>(d, a.M)) {
         double acc[1] = {0.0};
-        march_sweep(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &pa, const R2 &pb, const R4 &au) {
+        march_sweep<VAR>(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &pa, const R2 &pb, const R4 &au) {
             const V4 xv{{pa.v[0], pa.v[1], pb.v[0], pb.v[1]}};
             const V4 wv{{au.v[0], au.v[1], au.v[2], au.v[3]}};
 #pragma unroll
@@ -266,7 +266,7 @@ LG_REDUCE_KERNEL void proj_apply_march_kernel(ProjArgs a, Grid g, March m, const
         double acc[ND];
 #pragma unroll
         for (int j = 0; j < ND; ++j) acc[j] = 0.0;
-        march_sweep(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &pa, const R2 &pb, const R4 &au) {
+        march_sweep<VAR>(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &pa, const R2 &pb, const R4 &au) {
             V4 xc[D];
 #pragma unroll
             for (int j = 0; j < D; ++j) xc[j] = load4<DT>(colp<DT>(C, a.ld, j), c);
@@ -764,7 +764,8 @@ void proj_update_dt(const ProjBufs &p, const Grid *g, const double *x, const dou
     if (!Ax && march_ok(*g) && march_enabled()) {
         const March m = make_march(*g);
         ga = march_grid(m);
-        klaunch(ev, 0, proj_apply_march_kernel<DT, VF>, ga, kBlock, s, a, gg, m, x);
+        if (g->kx) klaunch(ev, 0, proj_apply_march_kernel<DT, VF, true>, ga, kBlock, s, a, gg, m, x);
+        else klaunch(ev, 0, proj_apply_march_kernel<DT, VF, false>, ga, kBlock, s, a, gg, m, x);
     } else if (Ax) {
         klaunch(ev, 0, proj_apply_kernel<DT, VF, false, true, true>, gr, kBlock, s, a, gg, x, Ax);
     } else if (g->kx) {

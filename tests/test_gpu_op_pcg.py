@@ -132,6 +132,56 @@ def test_pcg_box_grids(lib, shape):
         L.guess_op_destroy(A)
 
 
+@pytest.mark.parametrize("shape", BOXES)
+def test_box_var_operator_bit_exact(lib, shape):
+    import torch
+
+    announce(f"op var box {shape}")
+    L = lib
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    kappa = np.exp(0.5 * synth.random_vectors(7, 1, (nx + 2) * (ny + 2) * (nz + 2))[0])
+    A = L.guess_op_create(nx, ny, nz, 900.0, 10.0, dev(kappa))
+    try:
+        x = synth.random_vectors(nx + 2 * ny, 1, N)[0]
+        y = torch.empty(N, dtype=torch.float64, device="cuda")
+        L.op_apply(A, dev(x), y)
+        got = host(y)
+    finally:
+        L.guess_op_destroy(A)
+    want = op.apply_var_box(x, shape, op.face_coeffs_box(kappa, shape), 900.0)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("shape", [(384, 8, 6), (64, 16, 9), (6, 10, 7)])
+def test_pcg_box_var(lib, shape):
+    import torch
+
+    announce(f"pcg var box {shape}")
+    L = lib
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    c = 900.0
+    kappa = np.exp(0.5 * synth.random_vectors(8, 1, (nx + 2) * (ny + 2) * (nz + 2))[0])
+    faces = op.face_coeffs_box(kappa, shape)
+    apply = lambda v: op.apply_var_box(v, shape, faces, c)  # noqa: E731
+    kxa, kya, kza = faces
+    diag = c * (kxa[:, :, :-1] + kxa[:, :, 1:] + kya[:, :-1, :] + kya[:, 1:, :] + kza[:-1] + kza[1:]) + 10.0
+    b = synth.random_vectors(9, 1, N)[0]
+    A = L.guess_op_create(nx, ny, nz, c, 10.0, dev(kappa))
+    try:
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        st, it, _ = L.pcg_solve(A, dev(b), x, 1e-30, 5)
+        xo, _, _, _ = oracle_pcg(apply, b, np.zeros(N), 1.0 / diag.reshape(-1), 1e-30, 5)
+        assert st == L.ENOTCONV and rel_inf(host(x), xo) <= 1e-11
+        x.zero_()
+        st, it, rr = L.pcg_solve(A, dev(b), x, 1e-8, 5000)
+        xo, ito, sto, _ = oracle_pcg(apply, b, np.zeros(N), 1.0 / diag.reshape(-1), 1e-8, 5000)
+        assert st == L.OK and sto == 0 and abs(it - ito) <= 1
+    finally:
+        L.guess_op_destroy(A)
+
+
 def test_pcg_varcoef(lib):
     import torch
 
