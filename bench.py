@@ -85,6 +85,9 @@ def parse():
                    help="projection: relative rejection threshold of a new vector")
     p.add_argument("--precision-dtypes", default="f32,f16,bf16")
     p.add_argument("--progress", action="store_true", help="print a line to stderr after every step")
+    p.add_argument("--isolated", action="store_true",
+                   help="only time each guess kernel in isolation (MALL evicted between launches)")
+    p.add_argument("--reps", type=int, default=20)
     p.add_argument("--stop-rule", choices=("rhs", "initresid"), default="rhs",
                    help="PCG stop: ||r|| <= rtol ||b|| or ||r|| < rtol max(||r0||, 1)")
     p.add_argument("--rhs", choices=("planewave", "gaussian"), default="planewave",
@@ -210,6 +213,76 @@ def cpu_baseline(args, s_bytes):
     }
 
 
+def isolated(args, L):
+    """Each guess kernel in isolation: median of `reps` launches at the benchmark grid, with a
+    1 GiB scratch write between launches so that no operand is served from the 256 MB MALL.
+    Histories are random (well-conditioned); projection updates run at d = M - 1 (classic,
+    rejected duplicates keep d) and at d = M (rolling drop)."""
+    import torch
+
+    n, N, M = args.n, args.n ** 3, args.M
+    S = L.stream_handle()
+    scratch = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    A = L.guess_op_create(n, n, n, float((n + 1) ** 2), 10.0, None)
+    L.guess_op_set_stream(A, S)
+    b = torch.randn(N, dtype=torch.float64, device="cuda")
+    x0 = torch.empty_like(b)
+    reps = args.reps
+    out = {}
+
+    def med(v):
+        return sorted(v)[len(v) // 2]
+
+    for dt in ("f64", "f32", "f16", "bf16"):
+        s = L.ELEM_BYTES[L.DTYPES[dt]]
+        g = L.guess_create_ex(N, M, L.EXTRAP, args.degree, L.DTYPES[dt], 0.0, None, S)
+        L.guess_profile(g, True)
+        for _ in range(M):
+            L.guess_update(g, torch.randn(N, dtype=torch.float64, device="cuda"))
+        tf, tu = [], []
+        for _ in range(reps):
+            scratch.fill_(1.0)
+            L.guess_form(g, None, x0)
+            tf.append(L.guess_kernel_times(g)[0])
+            scratch.fill_(2.0)
+            L.guess_update(g, b)
+            tu.append(L.guess_kernel_times(g)[0])
+        out[f"extrap_form_{dt}"] = N * (M * s + 8) / (med(tf) * 1e-3) / 1e9
+        out[f"ring_store_{dt}"] = N * (8 + s) / (med(tu) * 1e-3) / 1e9
+        L.guess_destroy(g)
+    for meth in ("proj", "projqr"):
+        for dt in ("f64", "f32"):
+            s = L.ELEM_BYTES[L.DTYPES[dt]]
+            g = L.guess_create_ex(N, M, L.METHODS[meth], 0, L.DTYPES[dt], 1e-6, A, S)
+            L.guess_profile(g, True)
+            keep = []
+            for _ in range(M - 1 if meth == "proj" else M):
+                keep.append(torch.randn(N, dtype=torch.float64, device="cuda"))
+                L.guess_update(g, keep[-1])
+            d = L.guess_get_info(g)["count"]
+            tf, tu = [], []
+            for _ in range(reps):
+                scratch.fill_(1.0)
+                L.guess_form(g, b, x0)
+                tf.append(L.guess_kernel_times(g))
+                scratch.fill_(2.0)
+                L.guess_update(g, keep[-1] if meth == "proj" else torch.randn(N, dtype=torch.float64, device="cuda"))
+                tu.append(L.guess_kernel_times(g))
+            drop = meth == "projqr"
+            fb = kernel_bytes(meth, "form", N, s, d, M, False)
+            ub = kernel_bytes(meth, "update", N, s, d, M, False)
+            for name, by, i in zip(KERNELS[(meth, "form")], fb, range(3)):
+                if by:
+                    out[f"{meth}_{name}_{dt}_d{d}"] = by / (med([t[i] for t in tf]) * 1e-3) / 1e9
+            for name, by, i in zip(KERNELS[(meth, "update")], ub, range(6)):
+                if by:
+                    out[f"{meth}_{name}_{dt}_d{d}{'_drop' if drop else ''}"] = by / (med([t[i] for t in tu]) * 1e-3) / 1e9
+            L.guess_destroy(g)
+    L.guess_op_destroy(A)
+    print(json.dumps({"isolated_GBps": {k: round(v, 1) for k, v in out.items()}, "n": n, "M": M, "reps": reps,
+                      "copy_roof_GBps": copy_roof(L), "peak_GBps": HBM_PEAK_GBS}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -228,6 +301,9 @@ def main():
         gbps = copy_roof(L, 1 << 30, 5)
         print(json.dumps({"copy_kernel_GBps": gbps, "bytes_read_per_launch": 1 << 30,
                           "bytes_written_per_launch": 1 << 30}), flush=True)
+        return
+    if args.isolated:
+        isolated(args, L)
         return
     roof = copy_roof(L)
     n, N, M = args.n, args.n ** 3, args.M
