@@ -1,0 +1,34 @@
+"""bench.py's command-line contract on the CPU: more than one GPU is refused with a message,
+and the per-kernel byte model matches the closed forms stated for each kernel."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_multi_gpu_request_exits_with_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_byte_model_closed_forms():
+    N, s, M = 1000, 8, 8
+    # extrapolation: k stored slots + the FP64 guess; ring store: FP64 in, one slot out
+    assert bench.kernel_bytes("extrap", "form", N, s, 8, M, False) == [N * (8 * s + 8)]
+    assert bench.kernel_bytes("extrap", "update", N, s, 8, M, False) == [N * (8 + s)]
+    # projection form at d columns: dots d s + 8, combine d s + 8
+    assert sum(bench.kernel_bytes("proj", "form", N, s, 5, M, False)) == 2 * N * (5 * s + 8)
+    # classic Gram-Schmidt update at d: 5 d s + 2 s + 40; restart 8 + 2 s
+    assert sum(bench.kernel_bytes("proj", "update", N, s, 5, M, False)) == N * (5 * 5 * s + 2 * s + 40)
+    assert sum(bench.kernel_bytes("proj", "update", N, s, 0, M, True)) == N * (8 + 2 * s)
+    # l2 form reads B only in the second pass: 4 d s + 2 s + 40
+    assert sum(bench.kernel_bytes("proj_l2", "update", N, s, 5, M, False)) == N * (4 * 5 * s + 2 * s + 40)
+    # rolling drop at d = M: 7 M s + 40
+    assert sum(bench.kernel_bytes("projqr", "update", N, s, M, M, False)) == N * (7 * M * s + 40)
+    # variable coefficient: the fused apply also reads the face arrays
+    assert bench.kernel_bytes("proj", "update", N, s, 5, M, False, faces=123)[0] == N * (16 + 5 * s) + 123
