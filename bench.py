@@ -85,6 +85,11 @@ def parse():
                    help="projection: relative rejection threshold of a new vector")
     p.add_argument("--precision-dtypes", default="f32,f16,bf16")
     p.add_argument("--progress", action="store_true", help="print a line to stderr after every step")
+    p.add_argument("--fields", choices=("one", "ins"), default="one",
+                   help="ins: per step three velocity components (shift --velocity-shift) and a pressure "
+                        "(shift 0), each with its own right-hand sides and guess contexts")
+    p.add_argument("--velocity-shift", type=float, default=2.0e4,
+                   help="velocity Helmholtz shift, 1/(nu dt) for nu = 1e-2, dt = 5e-3")
     p.add_argument("--isolated", action="store_true",
                    help="only time each guess kernel in isolation (MALL evicted between launches)")
     p.add_argument("--reps", type=int, default=20)
@@ -323,7 +328,17 @@ def main():
         def rhs(t, out):
             L.workload_gaussian_rhs(n, synth.gaussian_center(gp, t), gp["sigma"], gp["amp"], out,
                                     L.stream_handle())
-    b = torch.empty(N, dtype=torch.float64, device="cuda")
+    # fields solved every step: one (the default), or the paper's incompressible-flow
+    # pattern of three velocity components (Helmholtz, shift 1/(nu dt)) and a pressure
+    # (Poisson), each with its own right-hand sides and its own guess contexts
+    fields = [("u", op, rhs)]
+    if args.fields == "ins":
+        op_v = Operator(n, args.velocity_shift)
+        op_p = Operator(n, 0.0)
+        fields = [(f"vel{c}", op_v, PlaneWaveRHS(synth.plane_wave_params(args.seed + 1 + c, args.modes), n))
+                  for c in range(3)]
+        fields.append(("p", op_p, PlaneWaveRHS(synth.plane_wave_params(args.seed + 4, args.modes), n)))
+    bufs = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in fields]
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
     def run(dtype, steps, warmup, shadow=False):
@@ -332,78 +347,85 @@ def main():
         reduced-precision history against it is recorded."""
         s = L.ELEM_BYTES[L.DTYPES[dtype]]
         ctx, xs, sh, x64 = {}, {}, {}, None
-        for m in methods:
-            meth, inner = L.parse_method(m)
-            ctx[m] = L.guess_create_ex(N, 1 if m == "last" else M, meth,
-                                       args.degree if m in ("extrap", "spextrap") else 0, L.DTYPES[dtype], args.eps_rel,
-                                       op.handle, L.stream_handle(), inner)
-            L.guess_profile(ctx[m], True)
-            xs[m] = torch.zeros(N, dtype=torch.float64, device="cuda")
-            if shadow:
-                sh[m] = L.guess_create_ex(N, 1 if m == "last" else M, meth,
-                                          args.degree if m in ("extrap", "spextrap") else 0, L.F64, args.eps_rel, op.handle,
-                                          L.stream_handle(), inner)
+        for fi, (_, fop, _) in enumerate(fields):
+            for m in methods:
+                meth, inner = L.parse_method(m)
+                ctx[fi, m] = L.guess_create_ex(N, 1 if m == "last" else M, meth,
+                                               args.degree if m in ("extrap", "spextrap") else 0, L.DTYPES[dtype],
+                                               args.eps_rel, fop.handle, L.stream_handle(), inner)
+                L.guess_profile(ctx[fi, m], True)
+                xs[fi, m] = torch.zeros(N, dtype=torch.float64, device="cuda")
+                if shadow:
+                    sh[fi, m] = L.guess_create_ex(N, 1 if m == "last" else M, meth,
+                                                  args.degree if m in ("extrap", "spextrap") else 0, L.F64,
+                                                  args.eps_rel, fop.handle, L.stream_handle(), inner)
         if shadow:
             x64 = torch.empty(N, dtype=torch.float64, device="cuda")
         stats = {m: {"iters": [], "guess_ms": 0.0, "guess_bytes": 0.0, "solve_ms": 0.0, "relres": [],
-                     "err": []} for m in methods}
+                     "err": [], "field_iters": {f[0]: [] for f in fields}} for m in methods}
         kstat = {}    # kernel -> [launches, ms, bytes]
 
         def one_step(step, timed):
             t = step * args.dt
-            rhs(t, b)
-            for m in methods:
-                g, x = ctx[m], xs[m]
-                inf0 = L.guess_get_info(g)
-                kd = inf0["count"]
-                if m == "spextrap":
-                    kd_form = min(args.degree, kd - 1) + 1 if kd > 0 else 0    # slots read
-                else:
-                    kd_form = kd if m.startswith("proj") else min(kd, M)
-                L.guess_form(g, b, x)
-                tf = L.guess_kernel_times(g)
-                if shadow and timed:
-                    L.guess_form(sh[m], b, x64)
-                    nrm = float(torch.linalg.vector_norm(x64))
-                    stats[m]["err"].append(float(torch.linalg.vector_norm(x - x64)) / nrm if nrm > 0 else 0.0)
-                ev[0].record()
-                st, it, rr = op.solve(b, x, args.rtol, args.maxit,
-                                      L.STOP_RHS if args.stop_rule == "rhs" else L.STOP_INITRESID)
-                ev[1].record()
-                inf1 = L.guess_get_info(g)
-                L.guess_update(g, x)
-                tu = L.guess_kernel_times(g)
-                if shadow:
-                    L.guess_update(sh[m], x)
-                if st != L.OK:
-                    raise RuntimeError(f"PCG failed for {m} ({dtype}) at step {step}: status {st}")
-                if not timed:
-                    continue
-                torch.cuda.synchronize()
-                S = stats[m]
-                S["iters"].append(it)
-                S["relres"].append(rr)
-                S["solve_ms"] += ev[0].elapsed_time(ev[1])
-                dd = inf1["count"]
-                if m.startswith("projqr"):
-                    restart = dd == 0 or M == 1
-                else:
-                    restart = m.startswith("proj") and (dd == 0 or dd >= M)
-                for call, times, kdd in (("form", tf, kd_form), ("update", tu, inf1["count"])):
-                    names = KERNELS[(m, call)]
-                    byts = kernel_bytes(m, call, N, s, kdd, M, restart, faces)
-                    for name, ms, by in zip(names, times, byts):
-                        # every kernel of the call counts in the guess time; the
-                        # per-kernel table keeps the streaming kernels that moved data
-                        S["guess_ms"] += ms
-                        S["guess_bytes"] += by
-                        if by == 0:
-                            continue
-                        key = name if m in ("extrap", "proj") else f"{name}:{m}"
-                        ks = kstat.setdefault(key, [0, 0.0, 0.0])
-                        ks[0] += 1
-                        ks[1] += ms
-                        ks[2] += by
+            for fi, (fname, fop, frhs) in enumerate(fields):
+                b = bufs[fi]
+                frhs(t, b)
+                for m in methods:
+                    field_step(step, timed, fi, fname, fop, b, m)
+
+        def field_step(step, timed, fi, fname, op, b, m):
+            g, x = ctx[fi, m], xs[fi, m]
+            inf0 = L.guess_get_info(g)
+            kd = inf0["count"]
+            if m == "spextrap":
+                kd_form = min(args.degree, kd - 1) + 1 if kd > 0 else 0    # slots read
+            else:
+                kd_form = kd if m.startswith("proj") else min(kd, M)
+            L.guess_form(g, b, x)
+            tf = L.guess_kernel_times(g)
+            if shadow and timed:
+                L.guess_form(sh[fi, m], b, x64)
+                nrm = float(torch.linalg.vector_norm(x64))
+                stats[m]["err"].append(float(torch.linalg.vector_norm(x - x64)) / nrm if nrm > 0 else 0.0)
+            ev[0].record()
+            st, it, rr = op.solve(b, x, args.rtol, args.maxit,
+                                  L.STOP_RHS if args.stop_rule == "rhs" else L.STOP_INITRESID)
+            ev[1].record()
+            inf1 = L.guess_get_info(g)
+            L.guess_update(g, x)
+            tu = L.guess_kernel_times(g)
+            if shadow:
+                L.guess_update(sh[fi, m], x)
+            if st != L.OK:
+                raise RuntimeError(f"PCG failed for {m} ({dtype}, field {fname}) at step {step}: status {st}")
+            if not timed:
+                return
+            torch.cuda.synchronize()
+            S = stats[m]
+            S["iters"].append(it)
+            S["field_iters"][fname].append(it)
+            S["relres"].append(rr)
+            S["solve_ms"] += ev[0].elapsed_time(ev[1])
+            dd = inf1["count"]
+            if m.startswith("projqr"):
+                restart = dd == 0 or M == 1
+            else:
+                restart = m.startswith("proj") and (dd == 0 or dd >= M)
+            for call, times, kdd in (("form", tf, kd_form), ("update", tu, inf1["count"])):
+                names = KERNELS[(m, call)]
+                byts = kernel_bytes(m, call, N, s, kdd, M, restart, faces)
+                for name, ms, by in zip(names, times, byts):
+                    # every kernel of the call counts in the guess time; the
+                    # per-kernel table keeps the streaming kernels that moved data
+                    S["guess_ms"] += ms
+                    S["guess_bytes"] += by
+                    if by == 0:
+                        continue
+                    key = name if m in ("extrap", "proj") else f"{name}:{m}"
+                    ks = kstat.setdefault(key, [0, 0.0, 0.0])
+                    ks[0] += 1
+                    ks[1] += ms
+                    ks[2] += by
 
         try:
             for step in range(1, warmup + 1):
@@ -419,7 +441,7 @@ def main():
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             for m in methods:
-                inf = L.guess_get_info(ctx[m])
+                inf = L.guess_get_info(ctx[0, m])
                 stats[m]["history"] = {k: inf[k] for k in ("count", "restarts", "drops", "rejects")}
         finally:
             torch.cuda.synchronize()
@@ -445,6 +467,8 @@ def main():
             "max_relres": float(np.max(S["relres"])),
             "history_after_run": S["history"],
         }
+        if len(fields) > 1:
+            per_method[m]["pcg_iters_per_step_by_field"] = {f: float(np.mean(v)) for f, v in S["field_iters"].items()}
     kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / v[0], "GBps": v[2] / (v[1] * 1e-3) / 1e9,
                    "bytes_per_launch": v[2] / v[0]} for k, v in sorted(kstat.items())}
     out = {
@@ -467,7 +491,7 @@ def main():
                                f"M={M}, EXTRAP({args.degree},{M}) + PROJ({M}), {args.dtype} history, PCG rtol {args.rtol}",
                    "n": n, "N": N, "M": M, "degree": args.degree, "methods": methods,
                    "history_dtype": args.dtype, "eps_rel": args.eps_rel, "rtol": args.rtol,
-                   "stop_rule": args.stop_rule, "rhs": args.rhs,
+                   "stop_rule": args.stop_rule, "rhs": args.rhs, "fields": [f[0] for f in fields],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": hbm_traffic(dname),
