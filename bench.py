@@ -93,6 +93,9 @@ def parse():
     p.add_argument("--isolated", action="store_true",
                    help="only time each guess kernel in isolation (MALL evicted between launches)")
     p.add_argument("--reps", type=int, default=20)
+    p.add_argument("--shard-nz", type=int, default=0,
+                   help="with --isolated: time the kernels on an n x n x NZ slab (one z-slab of a "
+                        "multi-GPU split) instead of the n^3 grid")
     p.add_argument("--stop-rule", choices=("rhs", "initresid"), default="rhs",
                    help="PCG stop: ||r|| <= rtol ||b|| or ||r|| < rtol max(||r0||, 1)")
     p.add_argument("--rhs", choices=("planewave", "gaussian"), default="planewave",
@@ -225,15 +228,17 @@ def isolated(args, L):
     rejected duplicates keep d) and at d = M (rolling drop)."""
     import torch
 
-    n, N, M = args.n, args.n ** 3, args.M
+    n, M = args.n, args.M
+    nz = args.shard_nz or n
+    N = n * n * nz
     S = L.stream_handle()
     scratch = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
-    A = L.guess_op_create(n, n, n, float((n + 1) ** 2), 10.0, None)
+    A = L.guess_op_create(n, n, nz, float((n + 1) ** 2), 10.0, None)
     L.guess_op_set_stream(A, S)
     b = torch.randn(N, dtype=torch.float64, device="cuda")
     x0 = torch.empty_like(b)
     reps = args.reps
-    out = {}
+    out, us = {}, {}
 
     def med(v):
         return sorted(v)[len(v) // 2]
@@ -254,6 +259,8 @@ def isolated(args, L):
             tu.append(L.guess_kernel_times(g)[0])
         out[f"extrap_form_{dt}"] = N * (M * s + 8) / (med(tf) * 1e-3) / 1e9
         out[f"ring_store_{dt}"] = N * (8 + s) / (med(tu) * 1e-3) / 1e9
+        us[f"extrap_form_{dt}"] = med(tf) * 1e3
+        us[f"ring_store_{dt}"] = med(tu) * 1e3
         L.guess_destroy(g)
     for meth in ("proj", "projqr"):
         for dt in ("f64", "f32"):
@@ -279,12 +286,25 @@ def isolated(args, L):
             for name, by, i in zip(KERNELS[(meth, "form")], fb, range(3)):
                 if by:
                     out[f"{meth}_{name}_{dt}_d{d}"] = by / (med([t[i] for t in tf]) * 1e-3) / 1e9
+                    us[f"{meth}_{name}_{dt}_d{d}"] = med([t[i] for t in tf]) * 1e3
             for name, by, i in zip(KERNELS[(meth, "update")], ub, range(6)):
                 if by:
-                    out[f"{meth}_{name}_{dt}_d{d}{'_drop' if drop else ''}"] = by / (med([t[i] for t in tu]) * 1e-3) / 1e9
+                    key = f"{meth}_{name}_{dt}_d{d}{'_drop' if drop else ''}"
+                    out[key] = by / (med([t[i] for t in tu]) * 1e-3) / 1e9
+                    us[key] = med([t[i] for t in tu]) * 1e3
             L.guess_destroy(g)
+    # one Jacobi-PCG iteration at this shape (wall time of a fixed-count solve, host loop included)
+    x = torch.zeros_like(b)
+    L.pcg_solve(A, b, x, rtol=1e-300, maxit=5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, its, _ = L.pcg_solve(A, b, x.zero_(), rtol=1e-300, maxit=100)
+    torch.cuda.synchronize()
+    us["pcg_iteration"] = (time.perf_counter() - t0) / max(its, 1) * 1e6
     L.guess_op_destroy(A)
-    print(json.dumps({"isolated_GBps": {k: round(v, 1) for k, v in out.items()}, "n": n, "M": M, "reps": reps,
+    print(json.dumps({"isolated_GBps": {k: round(v, 1) for k, v in out.items()},
+                      "isolated_us": {k: round(v, 2) for k, v in us.items()},
+                      "grid": [n, n, nz], "M": M, "reps": reps,
                       "copy_roof_GBps": copy_roof(L), "peak_GBps": HBM_PEAK_GBS}), flush=True)
 
 
