@@ -100,6 +100,16 @@ bool march_enabled() {
     return v;
 }
 
+int march_wgs_override() {
+    static const int v = env_int("LIBGUESS_MARCH_WGS", 0);
+    return v;
+}
+
+int march_nr_override() {
+    static const int v = env_int("LIBGUESS_MARCH_NR", 0);
+    return v;
+}
+
 }  // namespace lg
 
 // ====================================================================== operator

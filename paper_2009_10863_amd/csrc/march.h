@@ -17,6 +17,8 @@
 // results are bit-identical to it; only the traversal differs.
 #pragma once
 
+#include <atomic>
+
 #include "common.h"
 #include "stencil.h"
 
@@ -24,29 +26,71 @@ namespace lg {
 
 struct March {
     int tp;      // 256-element tiles per z-plane
-    int zlen;    // planes per work item
-    int items;   // tp * number of plane ranges
+    int nr;      // z ranges: range r covers planes [r*nz/nr, (r+1)*nz/nr)
+    int items;   // tp * nr work items (one tile over one z range)
 };
 
 inline bool march_ok(const Grid &g) {
     return g.aligned && g.nxy % 256 == 0 && (g.nxy / 256) % kWaves == 0;
 }
 
-inline March make_march(const Grid &g) {
+// LIBGUESS_MARCH_NR > 0 forces the number of z ranges (for measurements).
+int march_nr_override();
+
+// Work split: one work item (one tile over one z range) per wave.  A range
+// of about kMarchPlanes planes amortises the start of a sweep (two planes
+// loaded before the first result); more ranges are taken where that leaves
+// resident workgroup slots (`wgs`) empty, fewer where the workgroups would
+// exceed the partial-row capacity.  A plane too large for that capacity
+// makes the waves loop over several items.  (Measured on 256^3 and 384^3:
+// ranges of 16 planes or fewer, or splits that put several items on some
+// waves, cost up to 30 % in the stencil kernels.)
+constexpr int kMarchPlanes = 21;
+
+inline March make_march(const Grid &g, int wgs) {
     March m;
     m.tp = (int)(g.nxy / 256);
-    // about 1024 workgroups of kWaves items each
-    int nr = (1024 * kWaves) / m.tp;
-    nr = nr < 1 ? 1 : (nr > g.nz ? g.nz : nr);
-    m.zlen = (g.nz + nr - 1) / nr;
-    nr = (g.nz + m.zlen - 1) / m.zlen;
+    auto nwg = [&](int nr) { return ((int64_t)m.tp * nr + kWaves - 1) / kWaves; };
+    const int64_t fill = wgs < kMaxPartialBlocks ? (wgs < 1 ? 1 : wgs) : kMaxPartialBlocks;
+    int nr = (g.nz + kMarchPlanes / 2) / kMarchPlanes;
+    if (nr < 1) nr = 1;
+    while (nr < g.nz && nwg(nr) < fill) ++nr;
+    while (nr > 1 && nwg(nr) > kMaxPartialBlocks) --nr;
+    const int forced = march_nr_override();
+    if (forced > 0) nr = forced < g.nz ? forced : g.nz;
+    m.nr = nr;
     m.items = m.tp * nr;
     return m;
 }
 
+// Workgroups of kernel K (kBlock threads each) that are resident on the
+// device at once: the runtime's occupancy per CU times the CU count, queried
+// on first use (every device here is the same part).  LIBGUESS_MARCH_WGS
+// overrides it (for measurements).
+int march_wgs_override();
+
+template <auto K>
+int resident_wgs() {
+    static std::atomic<int> cached{0};
+    int n = cached.load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    n = march_wgs_override();
+    if (n <= 0) {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, K, kBlock, 0) != hipSuccess || per < 1) per = 4;
+        n = per * cus;
+    }
+    cached.store(n, std::memory_order_relaxed);
+    return n;
+}
+
+// Workgroups to launch: one per kWaves items, within the partial-row capacity.
 inline int march_grid(const March &m) {
-    const int wg = (m.items + kWaves - 1) / kWaves;
-    return wg < kMaxPartialBlocks ? wg : kMaxPartialBlocks;
+    const int n = (m.items + kWaves - 1) / kWaves;
+    return n < kMaxPartialBlocks ? n : kMaxPartialBlocks;
 }
 
 __device__ __forceinline__ R2 sel2(bool keep, const R2 &v) {
@@ -102,8 +146,8 @@ __device__ __forceinline__ void march_sweep(const Grid &g, const March &m, const
     const int64_t nxy = g.nxy;
     for (int item = lb * kWaves + wave; item < m.items; item += nwg * kWaves) {
         const int tau = item % m.tp, zr = item / m.tp;
-        const int z0 = zr * m.zlen;
-        const int z1 = z0 + m.zlen < nz ? z0 + m.zlen : nz;
+        const int z0 = (int)((int64_t)zr * nz / m.nr);
+        const int z1 = (int)((int64_t)(zr + 1) * nz / m.nr);
         const int64_t offa = (int64_t)tau * 256 + 2 * lane, offb = offa + 128;
         const uint32_t ja = fdiv(g.fnx, (uint32_t)offa), jb = fdiv(g.fnx, (uint32_t)offb);
         const int ia = (int)((uint32_t)offa - ja * (uint32_t)nx), ib = (int)((uint32_t)offb - jb * (uint32_t)nx);

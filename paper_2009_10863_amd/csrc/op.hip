@@ -101,7 +101,8 @@ __global__ __launch_bounds__(kBlock) void op_apply_march_kernel(Grid g, March m,
 template <bool VAR>
 static void op_apply_v(const Grid &g, const double *x, double *y, hipStream_t s) {
     if (march_ok(g) && march_enabled()) {
-        const March m = make_march(g);
+        const int wgs = resident_wgs<op_apply_march_kernel<VAR>>();
+        const March m = make_march(g, wgs);
         op_apply_march_kernel<VAR><<<march_grid(m), kBlock, 0, s>>>(g, m, x, y);
         return;
     }

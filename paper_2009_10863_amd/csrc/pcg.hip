@@ -313,9 +313,11 @@ LG_REDUCE_KERNEL void pcg_b_kernel(Grid g, double *__restrict__ r, const double 
 int launch_pcg_init(const Grid &g, const double *b, const double *x, double *r, double *part_b, hipStream_t s) {
     const int gr = pcg_grid(g);
     if (march_ok(g) && march_enabled()) {
-        // same number of partial rows as the chunk form (the consumers expect gr)
-        if (g.kx) pcg_init_march_kernel<true><<<gr, kBlock, 0, s>>>(g, make_march(g), b, x, r, part_b);
-        else pcg_init_march_kernel<false><<<gr, kBlock, 0, s>>>(g, make_march(g), b, x, r, part_b);
+        // same number of partial rows as the chunk form (the consumers expect
+        // gr); the items are split over all gr workgroups
+        const March m = make_march(g, gr);
+        if (g.kx) pcg_init_march_kernel<true><<<gr, kBlock, 0, s>>>(g, m, b, x, r, part_b);
+        else pcg_init_march_kernel<false><<<gr, kBlock, 0, s>>>(g, m, b, x, r, part_b);
         return GUESS_OK;
     }
     if (g.kx) {
@@ -336,7 +338,8 @@ static void pcg_iter_v(const Grid &g, double *x, double *r, double *const p[2], 
     const double *pold = p[(k - 1) & 1];
     int ga = gr;
     if (AL && march_ok(g) && march_enabled()) {
-        const March m = make_march(g);
+        const int wgs = resident_wgs<pcg_a_march_kernel<VAR>>();
+        const March m = make_march(g, wgs);
         ga = march_grid(m);
         pcg_a_march_kernel<VAR><<<ga, kBlock, 0, s>>>(g, m, x, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
     } else {

@@ -762,7 +762,9 @@ void proj_update_dt(const ProjBufs &p, const Grid *g, const double *x, const dou
     const Grid gg = g ? *g : Grid{};
     int ga = gr;   // partial rows written by the apply kernel
     if (!Ax && march_ok(*g) && march_enabled()) {
-        const March m = make_march(*g);
+        const int wgs = g->kx ? resident_wgs<proj_apply_march_kernel<DT, VF, true>>()
+                              : resident_wgs<proj_apply_march_kernel<DT, VF, false>>();
+        const March m = make_march(*g, wgs);
         ga = march_grid(m);
         if (g->kx) klaunch(ev, 0, proj_apply_march_kernel<DT, VF, true>, ga, kBlock, s, a, gg, m, x);
         else klaunch(ev, 0, proj_apply_march_kernel<DT, VF, false>, ga, kBlock, s, a, gg, m, x);
