@@ -128,8 +128,11 @@ def _check(code):
     return code
 
 
-def addr(v) -> int:
-    """Device address of a vector argument (int, None, or torch tensor)."""
+def addr(v, need=None, what="vector", f64=True) -> int:
+    """Device address of a vector argument (int, None, or torch tensor).  For a tensor,
+    `need` is the number of elements (float64 unless f64 is False, then bytes) that the
+    call reads or writes through it: a smaller tensor is refused here, since the library
+    cannot see the size of a device buffer."""
     if v is None:
         return None
     if isinstance(v, int):
@@ -138,11 +141,22 @@ def addr(v) -> int:
 
     if not isinstance(v, torch.Tensor):
         raise TypeError("expected a device address or a torch tensor")
+    if f64 and v.dtype != torch.float64:
+        raise TypeError(f"{what}: libguess vectors are float64, got {v.dtype}")
+    if need is not None:
+        have = v.numel() if f64 else v.numel() * v.element_size()
+        if have < need:
+            raise ValueError(f"{what}: the call needs {need} {'elements' if f64 else 'bytes'}, "
+                             f"the tensor has {have}")
     if not v.is_cuda:
         raise ValueError("libguess needs device (HIP) tensors")
     if not v.is_contiguous():
         raise ValueError("libguess needs contiguous tensors")
     return v.data_ptr()
+
+
+# unknowns of the operators and contexts made through this module (tensor size checks)
+_sizes: dict = {}
 
 
 def stream_handle(stream=None):
@@ -156,11 +170,14 @@ def stream_handle(stream=None):
 # ---------------------------------------------------------------- operator
 def guess_op_create(nx, ny, nz, inv_h2, shift, kappa=None) -> int:
     out = C.c_void_p()
-    _check(_lib.guess_op_create(nx, ny, nz, inv_h2, shift, addr(kappa), C.byref(out)))
+    kp = addr(kappa, (nx + 2) * (ny + 2) * (nz + 2) if min(nx, ny, nz) > 0 else None, "kappa")
+    _check(_lib.guess_op_create(nx, ny, nz, inv_h2, shift, kp, C.byref(out)))
+    _sizes[out.value] = nx * ny * nz
     return out.value
 
 
 def guess_op_destroy(A) -> None:
+    _sizes.pop(A, None)
     _lib.guess_op_destroy(A)
 
 
@@ -173,13 +190,16 @@ def guess_op_size(A) -> int:
 
 
 def op_apply(A, x, y) -> None:
-    _check(_lib.op_apply(A, addr(x), addr(y)))
+    n = _sizes.get(A)
+    _check(_lib.op_apply(A, addr(x, n, "x"), addr(y, n, "y")))
 
 
 def pcg_solve(A, b, x, rtol=1e-8, maxit=10000, stop_rule=STOP_RHS, check=True):
     """Returns (status, iterations, relres)."""
     it, rr = C.c_int(0), C.c_double(0.0)
-    code = _lib.pcg_solve_ex(A, addr(b), addr(x), rtol, maxit, stop_rule, C.byref(it), C.byref(rr))
+    n = _sizes.get(A)
+    code = _lib.pcg_solve_ex(A, addr(b, n, "b"), addr(x, n, "x"), rtol, maxit, stop_rule, C.byref(it),
+                             C.byref(rr))
     if check and code not in (OK, ENOTCONV, EBREAKDOWN):
         _check(code)
     return code, it.value, rr.value
@@ -190,6 +210,7 @@ def guess_create(N, M, method, degree) -> int:
     g = _lib.guess_create(N, M, method, degree)
     if not g:
         raise GuessError(EINVAL, _lib.guess_last_error().decode())
+    _sizes[g] = N
     return g
 
 
@@ -201,13 +222,15 @@ def guess_create_ex(N, M, method, degree=0, dtype=F64, eps_rel=0.0, op=None, str
     if workspace is not None and not isinstance(workspace, int):
         nbytes = workspace.numel() * workspace.element_size()
     o = guess_opts(N=N, M=M, method=method, degree=degree, dtype=dtype, eps_rel=eps_rel,
-                   op=op, stream=stream, inner=inner, workspace=addr(workspace), workspace_bytes=nbytes)
+                   op=op, stream=stream, inner=inner, workspace=addr(workspace, f64=False), workspace_bytes=nbytes)
     out = C.c_void_p()
     _check(_lib.guess_create_ex(C.byref(o), C.byref(out)))
+    _sizes[out.value] = N
     return out.value
 
 
 def guess_destroy(g) -> None:
+    _sizes.pop(g, None)
     _lib.guess_destroy(g)
 
 
@@ -224,11 +247,13 @@ def guess_workspace_bytes(N, M, method, dtype) -> int:
 
 
 def guess_form(g, b, x0) -> None:
-    _check(_lib.guess_form(g, addr(b), addr(x0)))
+    n = _sizes.get(g)
+    _check(_lib.guess_form(g, addr(b, n, "b"), addr(x0, n, "x0")))
 
 
 def guess_update(g, x, Ax=None) -> None:
-    _check(_lib.guess_update(g, addr(x), addr(Ax)))
+    n = _sizes.get(g)
+    _check(_lib.guess_update(g, addr(x, n, "x"), addr(Ax, n, "Ax")))
 
 
 def guess_get_info(g) -> dict:
@@ -254,7 +279,7 @@ def guess_spextrap_weights(m, k):
 
 
 def guess_history_get(g, which, j, out) -> None:
-    _check(_lib.guess_history_get(g, which, j, addr(out)))
+    _check(_lib.guess_history_get(g, which, j, addr(out, _sizes.get(g), "out")))
 
 
 def guess_proj_factor(g):
@@ -286,27 +311,33 @@ def workload_plane_wave_rhs(n, kvec, theta, amp, b, stream=None) -> None:
     kv = (C.c_int * (3 * K))(*[int(v) for v in kvec])
     th = (C.c_double * K)(*[float(v) for v in theta])
     am = (C.c_double * K)(*[float(v) for v in amp])
-    _check(_lib.workload_plane_wave_rhs(n, K, kv, th, am, addr(b), stream))
+    _check(_lib.workload_plane_wave_rhs(n, K, kv, th, am, addr(b, n ** 3 if n > 0 else None, "b"), stream))
 
 
 def workload_gaussian_rhs(n, center, sigma, amp, b, stream=None) -> None:
     c = (C.c_double * 3)(*[float(v) for v in center])
-    _check(_lib.workload_gaussian_rhs(n, c, float(sigma), float(amp), addr(b), stream))
+    _check(_lib.workload_gaussian_rhs(n, c, float(sigma), float(amp), addr(b, n ** 3 if n > 0 else None, "b"),
+                                      stream))
 
 
 def vec_multidot(N, K, V, y, stream=None):
     out = (C.c_double * K)()
-    _check(_lib.vec_multidot(N, K, addr(V), addr(y), out, stream))
+    ok = N > 0 and K > 0
+    _check(_lib.vec_multidot(N, K, addr(V, N * K if ok else None, "V"), addr(y, N if ok else None, "y"), out,
+                             stream))
     return list(out)
 
 
 def vec_combine(N, K, V, c, y, stream=None) -> None:
     cc = (C.c_double * K)(*[float(v) for v in c])
-    _check(_lib.vec_combine(N, K, addr(V), cc, addr(y), stream))
+    ok = N > 0 and K > 0
+    _check(_lib.vec_combine(N, K, addr(V, N * K if ok else None, "V"), cc, addr(y, N if ok else None, "y"),
+                            stream))
 
 
 def guess_copy_kernel(dst, src, nbytes, stream=None) -> None:
-    _check(_lib.guess_copy_kernel(addr(dst), addr(src), nbytes, stream))
+    _check(_lib.guess_copy_kernel(addr(dst, nbytes, "dst", f64=False), addr(src, nbytes, "src", f64=False),
+                                  nbytes, stream))
 
 
 def guess_strerror(code) -> str:

@@ -139,3 +139,39 @@ def test_workspace_route_argument_checks(L):
     assert lib.guess_create_ex(ctypes.byref(o), ctypes.byref(out)) == L.EINVAL and not out.value
     o.workspace, o.workspace_bytes = 4096 + 8, need
     assert lib.guess_create_ex(ctypes.byref(o), ctypes.byref(out)) == L.EINVAL and not out.value
+
+
+def test_binding_refuses_undersized_or_mistyped_tensors(L):
+    """The C ABI cannot see the size of a device buffer, so the binding checks every tensor it
+    forwards against what the call will touch, before the call (CPU tensors: the size and type
+    checks come first, so no device is needed here)."""
+    import torch
+
+    f64 = torch.float64
+    with pytest.raises(ValueError, match="kappa"):   # (n+2)^2 instead of (n+2)^3 values
+        L.guess_op_create(8, 8, 8, 81.0, 10.0, torch.zeros(10 * 10, dtype=f64))
+    with pytest.raises(TypeError, match="float64"):
+        L.guess_op_create(8, 8, 8, 81.0, 10.0, torch.zeros(10 ** 3, dtype=torch.float32))
+    with pytest.raises(ValueError, match="device"):  # right size: only the device check is left
+        L.guess_op_create(8, 8, 8, 81.0, 10.0, torch.zeros(10 ** 3, dtype=f64))
+    fake = 0x1234   # a handle the binding knows the size of; the library is never reached
+    L._sizes[fake] = 100
+    try:
+        short, ok = torch.zeros(99, dtype=f64), torch.zeros(100, dtype=f64)
+        # the first tensor that is checked is the short one (a good CPU tensor would stop at the
+        # device check)
+        for call in (lambda: L.op_apply(fake, short, ok), lambda: L.op_apply(fake, None, short),
+                     lambda: L.pcg_solve(fake, short, ok), lambda: L.pcg_solve(fake, None, short),
+                     lambda: L.guess_form(fake, short, ok), lambda: L.guess_form(fake, None, short),
+                     lambda: L.guess_update(fake, short), lambda: L.guess_update(fake, None, short),
+                     lambda: L.guess_history_get(fake, 0, 0, short)):
+            with pytest.raises(ValueError, match="needs 100"):
+                call()
+    finally:
+        L._sizes.pop(fake)
+    with pytest.raises(ValueError, match="needs 512"):
+        L.workload_gaussian_rhs(8, (0.5, 0.5, 0.5), 0.1, 1.0, torch.zeros(511, dtype=f64))
+    with pytest.raises(ValueError, match="needs 30"):
+        L.vec_multidot(10, 3, torch.zeros(29, dtype=f64), torch.zeros(10, dtype=f64))
+    with pytest.raises(ValueError, match="bytes"):
+        L.guess_copy_kernel(torch.zeros(8, dtype=torch.uint8), torch.zeros(16, dtype=torch.uint8), 16)
