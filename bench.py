@@ -223,7 +223,9 @@ def cpu_baseline(args, s_bytes):
 
 def isolated(args, L):
     """Each guess kernel in isolation: median of `reps` launches at the benchmark grid, with a
-    1 GiB scratch write between launches so that no operand is served from the 256 MB MALL.
+    1 GiB scratch read between launches so that no operand is served from the 256 MB MALL.  The
+    scratch is read, not written: a write would leave up to 256 MB of dirty lines whose write-back
+    would then run inside the timed launch.
     Histories are random (well-conditioned); projection updates run at d = M - 1 (classic,
     rejected duplicates keep d) and at d = M (rolling drop)."""
     import torch
@@ -232,7 +234,10 @@ def isolated(args, L):
     nz = args.shard_nz or n
     N = n * n * nz
     S = L.stream_handle()
-    scratch = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    scratch = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+
+    def evict():
+        scratch.sum()
     A = L.guess_op_create(n, n, nz, float((n + 1) ** 2), 10.0, None)
     L.guess_op_set_stream(A, S)
     b = torch.randn(N, dtype=torch.float64, device="cuda")
@@ -251,10 +256,10 @@ def isolated(args, L):
             L.guess_update(g, torch.randn(N, dtype=torch.float64, device="cuda"))
         tf, tu = [], []
         for _ in range(reps):
-            scratch.fill_(1.0)
+            evict()
             L.guess_form(g, None, x0)
             tf.append(L.guess_kernel_times(g)[0])
-            scratch.fill_(2.0)
+            evict()
             L.guess_update(g, b)
             tu.append(L.guess_kernel_times(g)[0])
         out[f"extrap_form_{dt}"] = N * (M * s + 8) / (med(tf) * 1e-3) / 1e9
@@ -274,10 +279,10 @@ def isolated(args, L):
             d = L.guess_get_info(g)["count"]
             tf, tu = [], []
             for _ in range(reps):
-                scratch.fill_(1.0)
+                evict()
                 L.guess_form(g, b, x0)
                 tf.append(L.guess_kernel_times(g))
-                scratch.fill_(2.0)
+                evict()
                 L.guess_update(g, keep[-1] if meth == "proj" else torch.randn(N, dtype=torch.float64, device="cuda"))
                 tu.append(L.guess_kernel_times(g))
             drop = meth == "projqr"
