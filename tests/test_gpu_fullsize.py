@@ -89,3 +89,97 @@ def test_proj_256_full(lib):
     finally:
         L.guess_destroy(g)
         L.guess_op_destroy(A)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_spextrap_256_sampled(lib, dtype):
+    """Sparse extrapolation SPEXTRAP(2,8) at full size: only the pivot slots enter the guess."""
+    import torch
+
+    announce(f"spextrap 256^3 M=8 m=2 {dtype}")
+    L = lib
+    M, m = 8, 2
+    idx = sample_idx()
+    g = L.guess_create_ex(N, M, L.SPEXTRAP, m, L.DTYPES[dtype])
+    x0 = torch.empty(N, dtype=torch.float64, device="cuda")
+    hist = []
+    try:
+        rng = np.random.default_rng(6)
+        for s in range(M + 2):
+            v = rng.standard_normal(N) * (1.0 + 0.1 * s)
+            L.guess_update(g, dev(v))
+            hist.append(lowprec.round_store(v[idx], dtype))
+            hist = hist[-M:]
+        L.guess_form(g, None, x0)
+        got = host(x0)[idx]
+    finally:
+        L.guess_destroy(g)
+    beta = extrap.to_f64(extrap.beta_sparse_exact(m, M))
+    assert np.count_nonzero(beta) == m + 1
+    want = extrap.form(hist, beta)
+    if dtype == "f64":
+        assert rel_inf(got, want) <= 1e-12
+    else:
+        mag = sum(abs(b) * np.abs(h) for b, h in zip(beta, hist))
+        assert_within(got, want, (M + 1) * 2.0 ** -24 * mag + 2.0 ** -24 * np.abs(want), hist, dtype)
+
+
+@pytest.mark.parametrize("method", ["projqr", "proj_l2", "projqr_l2"])
+def test_projection_variants_256_m8_properties(lib, method):
+    """The bench's configuration (256^3, M = 8) for the rolling window (two drops) and the l2
+    forms, ten random solutions: the stored history is orthonormal in the variant's inner product
+    with B = A X, and the guess meets the variant's Galerkin condition against the retained raw
+    solutions (A form: raw^T r = 0; l2 form: (A raw)^T r = 0, r = b - A x0).  The FP64 oracle
+    replays the same variants at 32^3 (test_gpu_proj_variants); at this size it would take
+    minutes per case, so properties that hold at any size are checked instead."""
+    import torch
+
+    announce(f"{method} 256^3 M=8 properties")
+    L = lib
+    M, T = 8, 10
+    meth, inner = L.parse_method(method)
+    A = L.guess_op_create(n, n, n, float((n + 1) ** 2), 10.0, None)
+    g = L.guess_create_ex(N, M, meth, 0, L.F64, 1e-6, A, None, inner)
+    S = L.stream_handle()
+    raw = torch.empty((T, N), dtype=torch.float64, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(12)
+    try:
+        for s in range(T):
+            raw[s].normal_(generator=gen)
+            L.guess_update(g, raw[s])
+        info = L.guess_get_info(g)
+        d = info["count"]
+        rolling = method.startswith("projqr")
+        assert d == (M if rolling else T - M)
+        assert info["drops"] == (T - M if rolling else 0)
+        window = raw[T - d:].contiguous()
+        X = torch.empty((d, N), dtype=torch.float64, device="cuda")
+        B = torch.empty((d, N), dtype=torch.float64, device="cuda")
+        for j in range(d):
+            L.guess_history_get(g, 0, j, X[j])
+            L.guess_history_get(g, 1, j, B[j])
+        l2 = inner == L.INNER_L2
+        G = np.stack([L.vec_multidot(N, d, B if l2 else X, B[j].contiguous(), S) for j in range(d)])
+        assert np.max(np.abs(G - np.eye(d))) <= 1e-12
+        AX = torch.empty(N, dtype=torch.float64, device="cuda")
+        for j in range(d):
+            L.op_apply(A, X[j], AX)
+            assert float(torch.max(torch.abs(AX - B[j]))) <= 1e-12 * float(torch.max(torch.abs(B[j])))
+        b = torch.empty(N, dtype=torch.float64, device="cuda").normal_(generator=gen)
+        x0 = torch.empty_like(b)
+        L.guess_form(g, b, x0)
+        L.op_apply(A, x0, AX)
+        r = (b - AX).contiguous()
+        if l2:
+            W = torch.empty_like(window)
+            for j in range(d):
+                L.op_apply(A, window[j], W[j])
+        else:
+            W = window
+        gal = np.array(L.vec_multidot(N, d, W, r, S))
+        scale = np.array([float(torch.linalg.vector_norm(W[j])) for j in range(d)]) * float(
+            torch.linalg.vector_norm(b))
+        assert np.max(np.abs(gal) / scale) <= 1e-10
+    finally:
+        L.guess_destroy(g)
+        L.guess_op_destroy(A)
