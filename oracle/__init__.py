@@ -14,14 +14,16 @@ common module is ``synth`` (seeded inputs, none of the method's arithmetic).
 
 Modules
 -------
-extrap      least-squares / naive extrapolation weights in exact rationals,
-            Lebesgue constant, the extrapolated guess, warm-up rule
+extrap      least-squares / naive / sparse (column-pivoted QR) extrapolation
+            weights in exact rationals, Lebesgue constant, the extrapolated
+            guess, warm-up rule
 lowprec     rounding of stored history to FP32 / FP16 / BF16
 operator    7-point constant- and variable-coefficient Helmholtz operators,
             Jacobi diagonal, exact DST-I solver for the constant case
 pcg         Jacobi-preconditioned conjugate gradients
-projection  Fischer's projection (classic restart variant) with the A inner
-            product, and the brute-force normal-equation minimiser
+projection  Fischer's projection: classic restarts (Algorithm 1) or the rolling
+            window with its QR update (Algorithm 2), in the A inner product or
+            the paper's l2 one, and the brute-force normal-equation minimiser
 sequence    the time-step driver: form guess -> solve -> update
 adjoint     reference gradient of the differentiation workload
 

@@ -8,8 +8,8 @@ the result is the FP64 reference.  L is exactly quadratic in c, which makes a
 central finite difference exact up to rounding (used as the pin).
 
 The paper does not differentiate through its solver; this workload and its
-reading are this library's extension.  Parity unpinned beyond the
-finite-difference check.
+reading are this library's extension.  The pin is the central finite
+difference, exact for this quadratic loss up to rounding.
 """
 from __future__ import annotations
 
