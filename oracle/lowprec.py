@@ -47,7 +47,8 @@ def stored_bits(x: np.ndarray, dtype: str, scale_exp: int = 0) -> np.ndarray:
     if dtype == "f32":
         return x32
     if dtype == "f16":
-        return x32.astype(np.float16)
+        with np.errstate(over="ignore"):   # beyond the FP16 range rounds to +-inf (IEEE)
+            return x32.astype(np.float16)
     if dtype == "bf16":
         return bf16_bits_from_f32(x32)
     raise ValueError(dtype)
