@@ -175,10 +175,18 @@ def cpu_baseline(args, s_bytes):
     algorithmic GB/s as the GPU value.
     """
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
+    with threadpool_limits(limits=1):   # one host thread throughout, BLAS included
+        return _cpu_baseline(args, np)
+
+
+def _cpu_baseline(args, np):
+    import synth
     from oracle import operator as oop
     from oracle.extrap import ExtrapHistory
     from oracle.projection import AOrthoProjection
+    from oracle.sequence import run_sequence
 
     n, M, m = args.n, args.M, args.degree
     N = n ** 3
@@ -210,6 +218,16 @@ def cpu_baseline(args, s_bytes):
         cores = len(os.sched_getaffinity(0))
     except Exception:
         cores = os.cpu_count()
+    # the whole small sequence (32^3, 4 plane waves, 50 steps, dt = 0.01): guess -> PCG -> update
+    n1 = 32
+    op1 = oop.Operator(n1)
+    p1 = synth.plane_wave_params(0, 4)
+    rhs1 = [synth.plane_wave_rhs(p1, n1, 0.01 * (k + 1)) for k in range(50)]
+    seq = {}
+    for meth in ("zero", "last", "extrap", "proj"):
+        t0 = time.perf_counter()
+        r = run_sequence(op1, rhs1, meth, M, m, rtol=args.rtol)
+        seq[meth] = {"wall_s": round(time.perf_counter() - t0, 3), "pcg_iters": int(sum(r["iters"]))}
     return {
         "value": nbytes / secs / 1e9,
         "unit": "GB/s",
@@ -217,7 +235,10 @@ def cpu_baseline(args, s_bytes):
         "cores_available": cores,
         "kind": "oracle",
         "sample": f"{args.cpu_steps} steady-state steps of EXTRAP({m},{M}) + PROJ({M}) form+update "
-                  f"at {n}^3, FP64 NumPy (elementwise streaming is single-threaded), {secs:.1f} s",
+                  f"at {n}^3, FP64 NumPy on one thread, {secs:.1f} s",
+        "small_sequence": {"workload": f"{n1}^3, 4 plane-wave modes, 50 steps, dt = 0.01, M = {M}, "
+                                       f"EXTRAP({m},{M}) / PROJ({M}), guess -> PCG -> update, one thread",
+                           "methods": seq},
     }
 
 
