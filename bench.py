@@ -135,7 +135,8 @@ def copy_roof(L, nbytes=1 << 30, reps=5):
 
 
 def hbm_traffic(kernel):
-    """Counter-measured HBM bytes per launch of `kernel`, if still valid.
+    """(counter-measured HBM bytes, algorithmic bytes) per launch of `kernel` in the profiled
+    run, if still valid.
 
     Read from profiles/hbm_traffic.txt (written from two rocprofv3 --pmc runs,
     FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration); the
@@ -163,7 +164,8 @@ def hbm_traffic(kernel):
     if rec.get("sha256") != h.hexdigest():
         return None
     v = rec.get(f"{kernel}.bytes_per_launch")
-    return float(v) if v else None
+    a = rec.get(f"{kernel}.algorithmic_bytes_per_launch")
+    return (float(v), float(a)) if v and a else None
 
 
 def cpu_baseline(args, s_bytes):
@@ -517,6 +519,11 @@ def main():
             per_method[m]["pcg_iters_per_step_by_field"] = {f: float(np.mean(v)) for f, v in S["field_iters"].items()}
     kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / v[0], "GBps": v[2] / (v[1] * 1e-3) / 1e9,
                    "bytes_per_launch": v[2] / v[0]} for k, v in sorted(kstat.items())}
+    # counter bytes of the profiled launches, scaled to this run's launches of the same kernel
+    # (their mix of history sizes d differs with the number of steps)
+    tr = hbm_traffic(dname)
+    traffic_ratio = tr[0] / tr[1] if tr else None
+    traffic = traffic_ratio * (dby / dl) if tr else None
     out = {
         "metric": "guess form+update HBM GB/s (256^3, M=8); PCG iters & ms/step vs FP64 plain",
         "value": value,
@@ -540,7 +547,7 @@ def main():
                    "stop_rule": args.stop_rule, "rhs": args.rhs, "fields": [f[0] for f in fields],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": hbm_traffic(dname),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_ratio": traffic_ratio,
                      "bytes_per_launch": dby / dl, "avg_us": 1e3 * dms / dl,
                      "copy_roof_GBps": roof, "frac_of_copy_roof": achieved / roof},
         "methods": per_method,
