@@ -94,7 +94,8 @@ enum {
  *   kappa != NULL:  (Au)_i = inv_h2 sum_faces k_f (u_i - u_nb) + shift u_i,
  *                   k_f = 2 k_i k_nb / (k_i + k_nb),
  * with kappa a device array of nodal values on all (nx+2)(ny+2)(nz+2) nodes
- * (boundary included, x fastest), read once here and not retained.  For the
+ * (boundary included, x fastest), read once here and not retained (its size
+ * cannot be checked here: a shorter array is read past its end).  For the
  * unit cube with n^3 interior nodes inv_h2 = (n+1)^2.  Neighbour order and
  * rounding are fixed: west, east, south, north, bottom, top, summed left to
  * right without fused multiply-add, then inv_h2 * s + shift * u.
