@@ -81,8 +81,9 @@ def parse():
     p.add_argument("--dt", type=float, default=0.005)
     p.add_argument("--seed", type=int, default=0)
     p.add_argument("--rtol", type=float, default=1e-8)
-    p.add_argument("--eps-rel", type=float, default=1e-6,
-                   help="projection: relative rejection threshold of a new vector")
+    p.add_argument("--eps-rel", type=float, default=0.0,
+                   help="projection: relative rejection threshold of a new vector (<= 0: the library's "
+                        "default for the storage format, 1e-6 for FP64)")
     p.add_argument("--precision-dtypes", default="f32,f16,bf16")
     p.add_argument("--progress", action="store_true", help="print a line to stderr after every step")
     p.add_argument("--fields", choices=("one", "ins"), default="one",
@@ -93,6 +94,11 @@ def parse():
     p.add_argument("--isolated", action="store_true",
                    help="only time each guess kernel in isolation (MALL evicted between launches)")
     p.add_argument("--reps", type=int, default=20)
+    p.add_argument("--adjoint", action="store_true",
+                   help="time the differentiable sequence instead: forward solves and the reverse-time "
+                        "adjoint solves, each with its own guess history, on --adjoint-n^3 for --adjoint-steps")
+    p.add_argument("--adjoint-n", type=int, default=128)
+    p.add_argument("--adjoint-steps", type=int, default=100)
     p.add_argument("--shard-nz", type=int, default=0,
                    help="with --isolated: time the kernels on an n x n x NZ slab (one z-slab of a "
                         "multi-GPU split) instead of the n^3 grid")
@@ -336,6 +342,60 @@ def isolated(args, L):
                       "copy_roof_GBps": copy_roof(L), "peak_GBps": HBM_PEAK_GBS}), flush=True)
 
 
+def adjoint_run(args, L):
+    """Differentiable sequence (loss sum_n ||x_n - y_n||^2, gradient with respect to the mode
+    amplitudes c): forward solves, then the reverse-time adjoint solves, each sequence with its own
+    guess history; the same with zero guesses for comparison.  Reports ms and PCG iterations per
+    step for both directions and how far the two gradients differ (both solve to rtol)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2009_10863_amd.autograd import GuessSolveFn, SolveSequence, plane_wave_modes
+    from paper_2009_10863_amd.sequence import Operator
+
+    n, T, K = args.adjoint_n, args.adjoint_steps, args.modes
+    N = n ** 3
+    S = L.stream_handle()
+    params = synth.plane_wave_params(args.seed, K)
+    tp = synth.target_params(args.seed + 99)
+    ts = synth.step_times(T, args.dt)
+    amps = np.stack([synth.mode_amplitudes(params, t) for t in ts])
+    F = plane_wave_modes(params, n)
+    Y = torch.empty((T, N), dtype=torch.float64, device="cuda")
+    kv = [int(v) for v in tp["k"].reshape(-1)]
+    for i, t in enumerate(ts):   # y(t) = scale sum_j sin(w_j t + phi_j) cos(2 pi k_j.x + theta_j)
+        L.workload_plane_wave_rhs(n, kv, tp["theta"], tp["scale"] * np.sin(tp["w"] * t + tp["phi"]), Y[i], S)
+    op = Operator(n)
+    out = {}
+    try:
+        for method in ("extrap", "zero"):
+            seq = SolveSequence(op, F, amps, method=method, M=args.M, degree=args.degree, rtol=args.rtol)
+            c = torch.ones(K, dtype=torch.float64, requires_grad=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            X = GuessSolveFn.apply(c, seq)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            loss = ((X - Y) ** 2).sum()
+            loss.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            out[method] = {"forward_ms_per_step": 1e3 * (t1 - t0) / T, "adjoint_ms_per_step": 1e3 * (t2 - t1) / T,
+                           "forward_iters_per_step": float(np.mean(seq.stats["forward_iters"])),
+                           "adjoint_iters_per_step": float(np.mean(seq.stats["adjoint_iters"])),
+                           "loss": float(loss.detach()), "grad": c.grad.tolist()}
+            del X, loss
+        ge, gz = np.array(out["extrap"]["grad"]), np.array(out["zero"]["grad"])
+        rel = float(np.max(np.abs(ge - gz)) / np.max(np.abs(gz)))
+    finally:
+        op.close()
+    print(json.dumps({"mode": "adjoint", "workload": f"{n}^3 Helmholtz, {K} plane-wave modes, {T} steps, dt={args.dt}, "
+                                                    f"EXTRAP({args.degree},{args.M}) both directions vs zero guess, "
+                                                    f"PCG rtol {args.rtol}",
+                      "methods": out, "grad_rel_diff_extrap_vs_zero": rel}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -357,6 +417,9 @@ def main():
         return
     if args.isolated:
         isolated(args, L)
+        return
+    if args.adjoint:
+        adjoint_run(args, L)
         return
     roof = copy_roof(L)
     n, N, M = args.n, args.n ** 3, args.M
@@ -490,7 +553,7 @@ def main():
             wall = time.perf_counter() - t0
             for m in methods:
                 inf = L.guess_get_info(ctx[0, m])
-                stats[m]["history"] = {k: inf[k] for k in ("count", "restarts", "drops", "rejects")}
+                stats[m]["history"] = {k: inf[k] for k in ("count", "restarts", "drops", "rejects", "eps_rel")}
         finally:
             torch.cuda.synchronize()
             for g in list(ctx.values()) + list(sh.values()):
@@ -543,7 +606,8 @@ def main():
                                f", dt={args.dt}, "
                                f"M={M}, EXTRAP({args.degree},{M}) + PROJ({M}), {args.dtype} history, PCG rtol {args.rtol}",
                    "n": n, "N": N, "M": M, "degree": args.degree, "methods": methods,
-                   "history_dtype": args.dtype, "eps_rel": args.eps_rel, "rtol": args.rtol,
+                   "history_dtype": args.dtype,
+                   "eps_rel": next(iter(per_method.values()))["history_after_run"]["eps_rel"], "rtol": args.rtol,
                    "stop_rule": args.stop_rule, "rhs": args.rhs, "fields": [f[0] for f in fields],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -573,7 +637,8 @@ def main():
                                 "guess_ms_per_step": S["guess_ms"] / args.precision_steps,
                                 "guess_rel_err_vs_f64_mean": float(np.mean(S["err"])),
                                 "guess_rel_err_vs_f64_max": float(np.max(S["err"])),
-                                "max_relres": float(np.max(S["relres"]))} for m, S in st_.items()},
+                                "max_relres": float(np.max(S["relres"])),
+                                "eps_rel": S["history"]["eps_rel"]} for m, S in st_.items()},
             }
         out["precision"] = {"steps": args.precision_steps, "warmup": args.warmup,
                             "reference": "FP64 history fed the same solutions", "dtypes": prec}

@@ -135,7 +135,9 @@ typedef struct guess_opts {
     int method;         /* GUESS_ZERO / LAST / EXTRAP / PROJ / SPEXTRAP / PROJ_QR    */
     int degree;         /* EXTRAP, SPEXTRAP: polynomial degree m, 0 <= m <= M - 1    */
     int dtype;          /* storage format of the history (GUESS_F64 ...)             */
-    double eps_rel;     /* PROJ: reject if nu <= eps_rel * nu0; <= 0 selects 1e-6    */
+    double eps_rel;     /* PROJ: reject if nu <= eps_rel * nu0; <= 0 selects the default
+                           of the storage format: 1e-6 (F64), 1e-4 (F32), 1e-2 (F16, BF16),
+                           which grows with its unit roundoff                         */
     guess_op_t op;      /* PROJ: operator applied in guess_update when Ax == NULL    */
     void *stream;       /* hipStream_t; NULL = null stream                           */
     int inner;          /* PROJ, PROJ_QR: GUESS_INNER_A (default) or GUESS_INNER_L2  */
@@ -214,6 +216,7 @@ typedef struct guess_info {
     double update_bytes;/* algorithmic HBM bytes of the last guess_update              */
     int drops;          /* PROJ_QR: oldest-solution drops so far                       */
     int inner;          /* PROJ, PROJ_QR: GUESS_INNER_A / GUESS_INNER_L2               */
+    double eps_rel;     /* PROJ, PROJ_QR: rejection threshold in use                   */
 } guess_info;
 
 /* Snapshot of the context state.  Synchronises the context's stream. */

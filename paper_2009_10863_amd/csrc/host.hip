@@ -503,6 +503,20 @@ static int proj_upload_state(guess_ctx *g) {
     return GUESS_OK;
 }
 
+// Rejection threshold when the caller gives none.  Rounding a stored column
+// to the storage format adds noise of relative size u_s, which the
+// normalisation of a column accepted with ratio nu/nu0 amplifies by nu0/nu;
+// the default therefore grows with the format's unit roundoff (the values
+// are the best of 1e-6 ... 1e-1 on the plane-wave sequences at 256^3).
+static double default_eps_rel(int dtype) {
+    switch (dtype) {
+        case GUESS_F32: return 1e-4;
+        case GUESS_F16:
+        case GUESS_BF16: return 1e-2;
+        default: return 1e-6;
+    }
+}
+
 extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
     if (!o || !out) return fail(GUESS_EINVAL, "guess_create_ex: NULL argument");
     *out = nullptr;
@@ -528,7 +542,7 @@ extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
     g->degree = degree;
     g->dtype = o->dtype;
     g->es = esize(o->dtype);
-    g->eps_rel = o->eps_rel > 0.0 ? o->eps_rel : 1e-6;
+    g->eps_rel = o->eps_rel > 0.0 ? o->eps_rel : default_eps_rel(o->dtype);
     g->inner = o->inner;
     g->vf = (o->method == GUESS_PROJ_QR ? 1 : 0) | (o->inner == GUESS_INNER_L2 ? 2 : 0);
     g->op = o->op;
@@ -731,6 +745,7 @@ extern "C" int guess_get_info(guess_t g, guess_info *info) {
     info->form_bytes = g->form_bytes;
     info->update_bytes = g->update_bytes;
     info->inner = g->inner;
+    info->eps_rel = g->eps_rel;
     if (proj_method(g->method)) {
         LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));
         LG_HIP(hipStreamSynchronize(g->stream));

@@ -56,7 +56,7 @@ class guess_info(C.Structure):
                 ("last_accepted", C.c_int), ("restarts", C.c_int), ("rejects", C.c_int),
                 ("nonfinite", C.c_int), ("nu", C.c_double), ("nu0", C.c_double),
                 ("form_bytes", C.c_double), ("update_bytes", C.c_double),
-                ("drops", C.c_int), ("inner", C.c_int)]
+                ("drops", C.c_int), ("inner", C.c_int), ("eps_rel", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

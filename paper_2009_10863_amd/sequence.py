@@ -53,10 +53,11 @@ class Operator:
 
 
 class GuessSequence:
-    """Initial-guess history for one sequence of solves (one field)."""
+    """Initial-guess history for one sequence of solves (one field).  eps_rel <= 0 selects the
+    library's rejection threshold for the storage format (1e-6 for FP64)."""
 
     def __init__(self, N: int, M: int = 8, method: str = "extrap", degree: int = 2,
-                 dtype: str = "f64", eps_rel: float = 1e-6, op: Operator = None, stream=None):
+                 dtype: str = "f64", eps_rel: float = 0.0, op: Operator = None, stream=None):
         self.N, self.M, self.method, self.degree, self.dtype = N, M, method, degree, dtype
         self.op = op
         self.stream = L.stream_handle(stream)
@@ -124,7 +125,7 @@ class PlaneWaveRHS:
 
 
 def run_sequence(op: Operator, rhs_fn, T: int, method: str = "extrap", M: int = 8, degree: int = 2,
-                 dtype: str = "f64", rtol: float = 1e-8, maxit: int = 20000, eps_rel: float = 1e-6,
+                 dtype: str = "f64", rtol: float = 1e-8, maxit: int = 20000, eps_rel: float = 0.0,
                  keep: bool = False, timing: bool = False):
     """Step loop: for n = 1..T, b = rhs_fn(n) -> guess -> PCG -> update.
 

@@ -84,3 +84,39 @@ def test_mode_generator_matches_inputs(lib):
     params = synth.plane_wave_params(2, 5)
     F = host(plane_wave_modes(params, 12))
     np.testing.assert_allclose(F, synth.plane_wave_modes(params, 12), rtol=0, atol=1e-13)
+
+
+def test_gradient_128_matches_reference(lib):
+    """The differentiation workload at its grid (128^3, 16 modes, EXTRAP(2,8) in both time
+    directions), 30 steps: loss and gradient against the oracle's DST-exact FP64 reference."""
+    import torch
+
+    from paper_2009_10863_amd.autograd import GuessSolveFn, SolveSequence
+    from paper_2009_10863_amd.sequence import Operator
+
+    announce("adjoint gradient 128^3 K=16 T=30")
+    n, T, K = 128, 30, 16
+    params = synth.plane_wave_params(0, K)
+    tparams = synth.target_params(99)
+    ts = synth.step_times(T, 0.005)
+    S = np.stack([synth.mode_amplitudes(params, t) for t in ts])
+    Fh = synth.plane_wave_modes(params, n)
+    Ft = synth.plane_wave_modes(tparams, n)
+    Y = np.stack([tparams["scale"] * synth.plane_wave_rhs(tparams, n, t, modes=Ft) for t in ts])
+    op = Operator(n)
+    try:
+        seq = SolveSequence(op, dev(Fh.reshape(-1)).reshape(K, -1), S, method="extrap", M=8, degree=2,
+                            rtol=1e-10)
+        c = torch.ones(K, dtype=torch.float64, requires_grad=True)
+        X = GuessSolveFn.apply(c, seq)
+        loss = ((X - dev(Y.reshape(-1)).reshape(Y.shape)) ** 2).sum()
+        loss.backward()
+        g = c.grad.numpy()
+        fwd, adj = seq.stats["forward_iters"], seq.stats["adjoint_iters"]
+    finally:
+        op.close()
+    Lref, gref = adjoint.loss_and_grad(Fh, S, Y, n, np.ones(K))
+    assert abs(float(loss) - Lref) <= 1e-8 * abs(Lref)
+    assert np.max(np.abs(g - gref)) <= 1e-7 * np.max(np.abs(gref))
+    # both directions profit from their guess histories once they are warm
+    assert np.mean(fwd[10:]) < 0.8 * fwd[0] and np.mean(adj[:-10]) < 0.8 * adj[-1]

@@ -184,3 +184,25 @@ def test_update_without_operator_needs_ax(lib):
         assert L.guess_get_info(g)["count"] == 1
     finally:
         L.guess_destroy(g)
+
+
+def test_default_threshold_follows_storage_format(lib):
+    """eps_rel <= 0 selects the format's default (1e-6 F64, 1e-4 F32, 1e-2 F16 / BF16); a given
+    value is kept."""
+    L = lib
+    A = L.guess_op_create(8, 8, 8, 81.0, 10.0, None)
+    try:
+        for dt, want in (("f64", 1e-6), ("f32", 1e-4), ("f16", 1e-2), ("bf16", 1e-2)):
+            for meth in (L.PROJ, L.PROJ_QR):
+                g = L.guess_create_ex(512, 4, meth, 0, L.DTYPES[dt], 0.0, A)
+                try:
+                    assert L.guess_get_info(g)["eps_rel"] == want
+                finally:
+                    L.guess_destroy(g)
+            g = L.guess_create_ex(512, 4, L.PROJ, 0, L.DTYPES[dt], 3e-5, A)
+            try:
+                assert L.guess_get_info(g)["eps_rel"] == 3e-5
+            finally:
+                L.guess_destroy(g)
+    finally:
+        L.guess_op_destroy(A)
