@@ -342,6 +342,35 @@ def isolated(args, L):
                       "copy_roof_GBps": copy_roof(L), "peak_GBps": HBM_PEAK_GBS}), flush=True)
 
 
+def small_sequence(args):
+    """The whole small sequence (32^3, 4 plane waves, 50 steps, dt = 0.01) through the library,
+    guess -> PCG -> update, per method: wall time and total PCG iterations (the oracle's run of the
+    same sequence is cpu_baseline's small_sequence entry)."""
+    import torch
+
+    import synth
+    from paper_2009_10863_amd.sequence import Operator, PlaneWaveRHS, run_sequence
+
+    n1 = 32
+    op1 = Operator(n1)
+    rhs = PlaneWaveRHS(synth.plane_wave_params(0, 4), n1)
+    res = {}
+    try:
+        for meth in ("zero", "last", "extrap", "proj"):
+            run_sequence(op1, lambda k, out: rhs(0.01 * k, out), 5, meth, args.M, args.degree, rtol=args.rtol)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = run_sequence(op1, lambda k, out: rhs(0.01 * k, out), 50, meth, args.M, args.degree,
+                             rtol=args.rtol)
+            torch.cuda.synchronize()
+            res[meth] = {"wall_s": round(time.perf_counter() - t0, 4), "pcg_iters": int(sum(r["iters"]))}
+    finally:
+        op1.close()
+    return {"workload": f"{n1}^3, 4 plane-wave modes, 50 steps, dt = 0.01, M = {args.M}, "
+                        f"EXTRAP({args.degree},{args.M}) / PROJ({args.M}), guess -> PCG -> update",
+            "methods": res}
+
+
 def adjoint_run(args, L):
     """Differentiable sequence (loss sum_n ||x_n - y_n||^2, gradient with respect to the mode
     amplitudes c): forward solves, then the reverse-time adjoint solves, each sequence with its own
@@ -642,6 +671,7 @@ def main():
             }
         out["precision"] = {"steps": args.precision_steps, "warmup": args.warmup,
                             "reference": "FP64 history fed the same solutions", "dtypes": prec}
+    out["small_sequence"] = small_sequence(args)
     if args.cpu:
         out["cpu_baseline"] = cpu_baseline(args, s)
     op.close()
