@@ -94,6 +94,10 @@ def parse():
     p.add_argument("--isolated", action="store_true",
                    help="only time each guess kernel in isolation (MALL evicted between launches)")
     p.add_argument("--reps", type=int, default=20)
+    p.add_argument("--concurrent", action="store_true",
+                   help="four independent fields (three velocity components, a pressure), each with its own "
+                        "operator, guess context and HIP stream: the steps run field after field on one host "
+                        "thread, then with one host thread per field; reports ms per step of both")
     p.add_argument("--adjoint", action="store_true",
                    help="time the differentiable sequence instead: forward solves and the reverse-time "
                         "adjoint solves, each with its own guess history, on --adjoint-n^3 for --adjoint-steps")
@@ -371,6 +375,98 @@ def small_sequence(args):
             "methods": res}
 
 
+def concurrent_run(args, L):
+    """Independent sequences solved side by side.  Each field owns an operator, an EXTRAP context, its
+    right-hand-side generator and a HIP stream; pcg_solve synchronises only its own stream, so one
+    host thread per field keeps all four streams busy at once.  The same steps are first run field
+    after field on one thread; iteration counts must agree between the two runs."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2009_10863_amd.sequence import GuessSequence, Operator, PlaneWaveRHS
+
+    n, T, W = args.n, args.steps, args.warmup
+    N = n ** 3
+    specs = [(f"vel{c}", args.velocity_shift, args.seed + 1 + c) for c in range(3)] + [("p", 0.0, args.seed + 4)]
+
+    def make():
+        fs = []
+        for name, shift, seed in specs:
+            st = torch.cuda.Stream()
+            op = Operator(n, shift, None, st)
+            fs.append({"name": name, "stream": st, "op": op,
+                       "rhs": PlaneWaveRHS(synth.plane_wave_params(seed, args.modes), n, st),
+                       "g": GuessSequence(N, args.M, "extrap", args.degree, "f64", 0.0, op, st),
+                       "b": torch.empty(N, dtype=torch.float64, device="cuda"),
+                       "x": torch.zeros(N, dtype=torch.float64, device="cuda"), "iters": []})
+        torch.cuda.synchronize()
+        return fs
+
+    def steps(f, first, count):
+        for step in range(first, first + count):
+            f["rhs"](step * args.dt, f["b"])
+            f["g"].form(f["b"], f["x"])
+            stt, it, _ = f["op"].solve(f["b"], f["x"], args.rtol, args.maxit)
+            if stt != L.OK:
+                raise RuntimeError(f"PCG failed for field {f['name']} at step {step}: status {stt}")
+            f["g"].update(f["x"])
+            f["iters"].append(it)
+        torch.cuda.synchronize(f["stream"])
+
+    def close(fs):
+        for f in fs:
+            f["g"].close()
+            f["op"].close()
+
+    out = {}
+    for mode in ("one_thread", "thread_per_field"):
+        fs = make()
+        try:
+            for f in fs:
+                steps(f, 1, W)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if mode == "one_thread":
+                for step in range(W + 1, W + T + 1):
+                    for f in fs:
+                        steps(f, step, 1)
+            else:
+                errs = []
+
+                def work(f):
+                    try:
+                        steps(f, W + 1, T)
+                    except Exception as e:  # noqa: BLE001
+                        errs.append(e)
+                th = [threading.Thread(target=work, args=(f,)) for f in fs]
+                for t in th:
+                    t.start()
+                for t in th:
+                    t.join()
+                if errs:
+                    raise errs[0]
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            out[mode] = {"ms_per_step": 1e3 * wall / T,
+                         "pcg_iters_per_step": {f["name"]: float(np.mean(f["iters"][W:])) for f in fs},
+                         "iters": {f["name"]: f["iters"] for f in fs}}
+        finally:
+            close(fs)
+    same = out["one_thread"]["iters"] == out["thread_per_field"]["iters"]
+    for v in out.values():
+        del v["iters"]
+    print(json.dumps({"mode": "concurrent", "workload": f"{n}^3: three velocity components (shift "
+                                                       f"{args.velocity_shift}) and a pressure, {args.modes} "
+                                                       f"plane-wave modes each, EXTRAP({args.degree},{args.M}), "
+                                                       f"{T} timed steps after {W}",
+                      "runs": out, "same_iterations": same,
+                      "speedup": out["one_thread"]["ms_per_step"] / out["thread_per_field"]["ms_per_step"]}),
+          flush=True)
+
+
 def adjoint_run(args, L):
     """Differentiable sequence (loss sum_n ||x_n - y_n||^2, gradient with respect to the mode
     amplitudes c): forward solves, then the reverse-time adjoint solves, each sequence with its own
@@ -449,6 +545,9 @@ def main():
         return
     if args.adjoint:
         adjoint_run(args, L)
+        return
+    if args.concurrent:
+        concurrent_run(args, L)
         return
     roof = copy_roof(L)
     n, N, M = args.n, args.n ** 3, args.M

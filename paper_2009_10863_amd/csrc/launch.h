@@ -60,7 +60,9 @@ struct ProjState {
 struct PcgState {
     double rho[2];
     double alpha, rr, bb, rr0, thresh;
-    int it, converged, breakdown, rule;
+    int it;
+    int converged;          // 0, or the iteration k whose stop test (on r_{k-1}) passed
+    int breakdown, rule;
     int x_pending;          // x still lacks alpha_k p_k of the last completed iteration
 };
 

@@ -6,6 +6,12 @@
 // iterations in batches and only reads the state between batches; the
 // iteration count is still exact.
 //
+// A kernel returns early only on what an earlier kernel decided: the
+// convergence flag holds the iteration whose stop test passed, so the
+// workgroups of that same pcg_a launch -- including any that start after
+// workgroup 0 has written the flag -- all still apply their share of the
+// last x update.
+//
 // This translation unit is compiled with the max-ILP instruction scheduler:
 // the search-direction stencil issues ~30 loads per chunk, and grouping them
 // measured 6 % faster per iteration than the default schedule at 256^3.
@@ -38,7 +44,14 @@ static __device__ __forceinline__ V4 toV(const R4 &r) { return V4{{r.v[0], r.v[1
 // x receives exactly the same FMAs as in the textbook order.
 int pcg_grid(const Grid &g) { return stream_grid(nchunks(g.n), reduce_blocks()); }
 
-__device__ __forceinline__ bool pcg_done(const PcgState *st) { return st->converged | st->breakdown; }
+// Solve over before iteration k's pcg_a (stopped at an earlier iteration)...
+__device__ __forceinline__ bool pcg_done_before_a(const PcgState *st, int k) {
+    return st->breakdown || (st->converged != 0 && st->converged < k);
+}
+// ... and before iteration k's pcg_b (stopped at iteration k or earlier).
+__device__ __forceinline__ bool pcg_done_before_b(const PcgState *st, int k) {
+    return st->breakdown || (st->converged != 0 && st->converged <= k);
+}
 
 template <bool VAR>
 __device__ __forceinline__ V4 dinv4(const Grid &g, int64_t c) {
@@ -132,7 +145,7 @@ __device__ __forceinline__ bool pcg_a_begin(const double *part_b, int nb, PcgSta
         }
         st->rr = rr;
         if (stop) {
-            st->converged = 1;
+            st->converged = k;
             st->it = k - 1;
         } else {
             st->rho[k & 1] = rz;
@@ -167,7 +180,7 @@ LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, double *__restrict__ x, const double 
                                    double *__restrict__ q, const double *part_b, int nb_b, double *part_a,
                                    PcgState *st, int k, double rtol) {
     __shared__ double lds[kLdsDoubles];
-    if (pcg_done(st)) return;
+    if (pcg_done_before_a(st, k)) return;
     double beta;
     const double alpha = k > 1 ? st->alpha : 0.0;   // alpha_{k-1}
     if (k > 1 && blockIdx.x == 0 && threadIdx.x == 0) st->x_pending = 0;
@@ -215,7 +228,7 @@ LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, double *__restrict__ x
                                          double *__restrict__ q, const double *part_b, int nb_b, double *part_a,
                                          PcgState *st, int k, double rtol) {
     __shared__ double lds[kLdsDoubles];
-    if (pcg_done(st)) return;
+    if (pcg_done_before_a(st, k)) return;
     double beta;
     const double alpha = k > 1 ? st->alpha : 0.0;   // alpha_{k-1}
     if (k > 1 && blockIdx.x == 0 && threadIdx.x == 0) st->x_pending = 0;
@@ -271,7 +284,7 @@ template <bool VAR>
 LG_REDUCE_KERNEL void pcg_b_kernel(Grid g, double *__restrict__ r, const double *__restrict__ q,
                                    const double *part_a, int nb_a, double *part_b, PcgState *st, int k) {
     __shared__ double lds[kLdsDoubles];
-    if (pcg_done(st)) return;
+    if (pcg_done_before_b(st, k)) return;
     double tot[1];
     final_sums<1>(part_a, nb_a, tot, lds);
     const double pq = tot[0];
@@ -364,7 +377,7 @@ int launch_pcg_iter(const Grid &g, double *x, double *r, double *const p[2], dou
 __global__ __launch_bounds__(kBlock) void pcg_check_kernel(const double *part_b, int nb, PcgState *st, int k,
                                                            double rtol) {
     __shared__ double lds[kLdsDoubles];
-    if (pcg_done(st)) return;
+    if (st->converged != 0 || st->breakdown) return;
     double tot[3];
     final_sums<3>(part_b, nb, tot, lds);
     if (threadIdx.x == 0) {
@@ -378,7 +391,7 @@ __global__ __launch_bounds__(kBlock) void pcg_check_kernel(const double *part_b,
             st->rr0 = tot[0];
         }
         if (stop) {
-            st->converged = 1;
+            st->converged = k;
             st->it = k - 1;
         }
     }

@@ -155,3 +155,23 @@ def test_pcg_384_true_residual(lib, gpu_op):
     L.op_apply(gpu_op, x, Ax)
     true = float(torch.linalg.vector_norm(b - Ax) / torch.linalg.vector_norm(b))
     assert true <= 2e-8, (it, true)
+
+
+def test_pcg_384_stop_path_applies_last_update_everywhere(lib, gpu_op):
+    """The solve that stops inside its stencil kernel (the stop test of iteration K+1 passes) must
+    give bit for bit the x of the same solve capped at K iterations, which ends with the separate
+    check and finishing kernels.  At this size the stencil kernel's workgroups run in several
+    rounds, so workgroups that start after the stop decision was written must still apply their
+    part of the last x update."""
+    import torch
+
+    announce("pcg 384^3 varcoef stop path")
+    L = lib
+    b = torch.empty(N, dtype=torch.float64, device="cuda").normal_(generator=torch.Generator(device="cuda").manual_seed(21))
+    x1 = torch.zeros(N, dtype=torch.float64, device="cuda")
+    st, its, rr = L.pcg_solve(gpu_op, b, x1, 1e-6, 20000)
+    assert st == L.OK and its > 1
+    x2 = torch.zeros(N, dtype=torch.float64, device="cuda")
+    st2, its2, rr2 = L.pcg_solve(gpu_op, b, x2, 1e-6, its)
+    assert st2 == L.OK and its2 == its and rr2 == rr
+    assert torch.equal(x1, x2)

@@ -128,6 +128,10 @@ def test_pcg_box_grids(lib, shape):
         xo, ito, sto, _ = oracle_pcg(apply, b, np.zeros(N), dinv, 1e-8, 5000)
         assert st == L.OK and sto == 0 and abs(it - ito) <= 1
         assert np.linalg.norm(b - apply(host(x))) <= 1.5e-8 * np.linalg.norm(b)
+        # stopping inside the stencil kernel and stopping at the iteration cap give the same x
+        x2 = torch.zeros(N, dtype=torch.float64, device="cuda")
+        st2, it2, _ = L.pcg_solve(A, dev(b), x2, 1e-8, it)
+        assert st2 == L.OK and it2 == it and torch.equal(x, x2)
     finally:
         L.guess_op_destroy(A)
 
