@@ -116,6 +116,8 @@ def parse():
     p.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     p.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
     p.add_argument("--cpu-steps", type=int, default=12)
+    p.add_argument("--no-small-sequence", dest="small", action="store_false", default=True,
+                   help="skip the 32^3 whole-sequence run (e.g. under a profiler)")
     p.add_argument("--precision-steps", type=int, default=10,
                    help="timed steps of each FP32/FP16/BF16 history run (0: skip)")
     p.add_argument("--calibrate-copy", action="store_true",
@@ -770,7 +772,8 @@ def main():
             }
         out["precision"] = {"steps": args.precision_steps, "warmup": args.warmup,
                             "reference": "FP64 history fed the same solutions", "dtypes": prec}
-    out["small_sequence"] = small_sequence(args)
+    if args.small:
+        out["small_sequence"] = small_sequence(args)
     if args.cpu:
         out["cpu_baseline"] = cpu_baseline(args, s)
     op.close()
