@@ -282,7 +282,9 @@ int guess_kernel_times(guess_t g, double *ms, int max, int *n);
  *   b_i = sum_k a_k cos(2 pi (kx_k x + ky_k y + kz_k z) + theta_k)
  * at interior node (x, y, z) = (i, j, l) / (n + 1).  kvec: host int array
  * 3K (kx, ky, kz per mode); theta, amp: host arrays of K doubles.  b is a
- * device vector of n^3 doubles.  K <= 64.  Enqueued on `stream`.
+ * device vector of n^3 doubles.  K <= 64.  Enqueued on `stream`.  The
+ * per-axis tables are kept per host thread; a call with other modes first
+ * waits for the previous call's kernel.
  */
 int workload_plane_wave_rhs(int n, int K, const int *kvec, const double *theta,
                             const double *amp, double *b, void *stream);
@@ -294,7 +296,8 @@ int workload_plane_wave_rhs(int n, int K, const int *kvec, const double *theta,
  *   b_i = amp * (g_x(i) * (g_y(j) * g_z(l))),  g_a(i) = exp(-(x_i - c_a)^2 / (2 sigma^2)),
  * x_i = (i + 1) / (n + 1), on the n^3 interior nodes, x fastest.  b is a
  * device vector of n^3 doubles; a small per-thread table buffer is kept
- * between calls.  Enqueued on `stream`; EINVAL for bad arguments.
+ * between calls (a call on another stream than the previous one first waits
+ * for that call's kernels).  Enqueued on `stream`; EINVAL for bad arguments.
  */
 int workload_gaussian_rhs(int n, const double *center, double sigma, double amp, double *b, void *stream);
 

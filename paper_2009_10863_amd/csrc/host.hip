@@ -873,13 +873,27 @@ extern "C" int guess_proj_factor(guess_t g, double *R, int *d) {
 
 // ====================================================================== workload
 namespace {
+// The workload generators keep device tables per host thread.  A table is
+// rewritten only after the kernels of the previous call that read it have
+// finished: `done` is recorded after every launch, so a call on another
+// stream (or with other parameters) first waits for it.
 struct PlaneWaveTables {
     int n = -1, K = -1;
     std::vector<int> kvec;
     std::vector<double> theta;
     double *dev = nullptr;  // 3 tables of K*n complex values
+    hipEvent_t done = nullptr;
 };
 thread_local PlaneWaveTables g_pw;
+
+int record_done(hipEvent_t &ev, hipStream_t s) {
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        ev = nullptr;
+        return fail(GUESS_EHIP, "workload: event creation failed");
+    }
+    LG_HIP(hipEventRecord(ev, s));
+    return GUESS_OK;
+}
 }  // namespace
 
 extern "C" int workload_plane_wave_rhs(int n, int K, const int *kvec, const double *theta, const double *amp,
@@ -892,7 +906,7 @@ extern "C" int workload_plane_wave_rhs(int n, int K, const int *kvec, const doub
                       std::equal(theta, theta + K, g_pw.theta.begin());
     if (!same) {
         if (g_pw.dev) {
-            LG_HIP(hipStreamSynchronize(s));
+            if (g_pw.done) LG_HIP(hipEventSynchronize(g_pw.done));
             (void)hipFree(g_pw.dev);
             g_pw.dev = nullptr;
         }
@@ -920,13 +934,16 @@ extern "C" int workload_plane_wave_rhs(int n, int K, const int *kvec, const doub
     }
     const size_t tsz = (size_t)K * n * 2;
     LG_TRY(lg::launch_plane_wave_rhs(n, K, g_pw.dev, g_pw.dev + tsz, g_pw.dev + 2 * tsz, amp, b, s));
-    return check_launch("workload_plane_wave_rhs");
+    LG_TRY(check_launch("workload_plane_wave_rhs"));
+    return record_done(g_pw.done, s);
 }
 
 namespace {
 struct GaussTables {
     int n = 0;
     double *dev = nullptr;
+    hipStream_t last = nullptr;   // stream of the previous call (compared, never used)
+    hipEvent_t done = nullptr;
 };
 thread_local GaussTables g_gauss;
 }  // namespace
@@ -936,9 +953,12 @@ extern "C" int workload_gaussian_rhs(int n, const double *center, double sigma, 
     if (n < 1 || !center || !b || !(sigma > 0.0) || !std::isfinite(sigma))
         return fail(GUESS_EINVAL, "workload_gaussian_rhs: bad argument");
     hipStream_t s = (hipStream_t)stream;
+    // every call rewrites the tables: on the previous call's stream that is ordered, on another
+    // stream wait for the previous call's kernels first
+    if (g_gauss.done && (g_gauss.last != s || !g_gauss.dev || g_gauss.n < n))
+        LG_HIP(hipEventSynchronize(g_gauss.done));
     if (!g_gauss.dev || g_gauss.n < n) {
         if (g_gauss.dev) {
-            LG_HIP(hipStreamSynchronize(s));
             (void)hipFree(g_gauss.dev);
             g_gauss.dev = nullptr;
         }
@@ -949,7 +969,9 @@ extern "C" int workload_gaussian_rhs(int n, const double *center, double sigma, 
         g_gauss.n = n;
     }
     LG_TRY(lg::launch_gaussian_rhs(n, center, sigma, amp, g_gauss.dev, b, s));
-    return check_launch("workload_gaussian_rhs");
+    LG_TRY(check_launch("workload_gaussian_rhs"));
+    g_gauss.last = s;
+    return record_done(g_gauss.done, s);
 }
 
 // ====================================================================== vectors

@@ -35,6 +35,51 @@ def test_gaussian_rhs_kernel(lib, n):
         lib.workload_gaussian_rhs(n, [0.5, 0.5, 0.5], 0.0, 1.0, b, lib.stream_handle())
 
 
+def test_workload_generators_across_streams(lib):
+    """One host thread alternating streams (and, for the plane waves, mode sets): every right-hand
+    side equals the one made alone on a single stream (the per-thread tables are rewritten only
+    after the previous call's kernels are done)."""
+    import torch
+
+    announce("workload generators across streams")
+    L = lib
+    n = 96
+    N = n ** 3
+    gp = synth.gaussian_source_params(4)
+    pw = [synth.plane_wave_params(s, 16) for s in (1, 2)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+    def gauss(t, out, st):
+        L.workload_gaussian_rhs(n, synth.gaussian_center(gp, t), gp["sigma"], gp["amp"], out, L.stream_handle(st))
+
+    def plane(q, t, out, st):
+        p = pw[q]
+        L.workload_plane_wave_rhs(n, [int(v) for v in p["k"].reshape(-1)], p["theta"],
+                                  np.sin(p["w"] * t + p["phi"]), out, L.stream_handle(st))
+
+    ts = [0.1 * (i + 1) for i in range(6)]
+    ref_g, ref_p = [], []
+    for i, t in enumerate(ts):
+        out = torch.empty(N, dtype=torch.float64, device="cuda")
+        gauss(t, out, None)
+        torch.cuda.synchronize()
+        ref_g.append(host(out))
+        out = torch.empty(N, dtype=torch.float64, device="cuda")
+        plane(i % 2, t, out, None)
+        torch.cuda.synchronize()
+        ref_p.append(host(out))
+    outs_g = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in ts]
+    outs_p = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in ts]
+    torch.cuda.synchronize()
+    for i, t in enumerate(ts):
+        gauss(t, outs_g[i], streams[i % 2])
+        plane(i % 2, t, outs_p[i], streams[(i + 1) % 2])
+    torch.cuda.synchronize()
+    for i in range(len(ts)):
+        assert np.array_equal(host(outs_g[i]), ref_g[i]), i
+        assert np.array_equal(host(outs_p[i]), ref_p[i]), i
+
+
 def _sequence(n, T, dt, seed=1):
     params = synth.gaussian_source_params(seed)
     B = [synth.gaussian_source_rhs(params, n, t) for t in synth.step_times(T, dt)]
