@@ -159,7 +159,8 @@ void guess_destroy(guess_t g);
 int guess_set_stream(guess_t g, void *stream);
 int guess_set_op(guess_t g, guess_op_t A);
 /* Device bytes the history and scratch of such a context occupy (the size a
- * caller workspace must have; buffers inside it are 256-byte aligned). */
+ * caller workspace must have; buffers inside it are 256-byte aligned).  An
+ * FP64 extrapolation ring has M + 1 slots (see guess_next_slot). */
 size_t guess_workspace_bytes(int64_t N, int M, int method, int dtype);
 
 /*
@@ -180,7 +181,8 @@ int guess_form(guess_t g, const double *b, double *x0);
 
 /*
  * Add the solution x of the latest solve to the history.
- *   EXTRAP / LAST: x is rounded to the storage format into the next ring slot.
+ *   EXTRAP / LAST: x is rounded to the storage format into the next ring slot;
+ *     when x is that slot (guess_next_slot) nothing is copied.
  *   PROJ: Ax = A x if the caller has it (Ax = b is allowed, then
  *     X^T A X = I holds only to the solve tolerance); Ax == NULL makes the
  *     library apply the bound operator once (EINVAL if none is bound).
@@ -202,11 +204,23 @@ int guess_form(guess_t g, const double *b, double *x0);
  */
 int guess_update(guess_t g, const double *x, const double *Ax);
 
+/*
+ * Solving in place (§4: extrapolation then moves (M+1) N values per step and
+ * the update copies nothing).  An FP64 extrapolation ring (EXTRAP, LAST,
+ * SPEXTRAP) keeps one slot more than M: the slot the next update writes,
+ * which no guess reads.  *slot receives its device address (N doubles);
+ * the caller may form the guess into it, solve there, and pass it to
+ * guess_update, which then only advances the ring.  The address changes
+ * with every update.  EINVAL for other methods or storage formats.
+ */
+int guess_next_slot(guess_t g, double **slot);
+
 typedef struct guess_info {
     int64_t N;
     int method, dtype, M, degree;
     int count;          /* EXTRAP/LAST: stored solutions (<= M); PROJ: columns d      */
-    int head;           /* EXTRAP/LAST: ring slot the next update writes              */
+    int head;           /* EXTRAP/LAST: ring slot the next update writes (of M + 1
+                           slots for FP64 history, M otherwise)                       */
     int last_accepted;  /* PROJ: 1 if the last update stored its vector                */
     int restarts;       /* PROJ: restarts so far                                       */
     int rejects;        /* PROJ: rejected vectors so far                               */

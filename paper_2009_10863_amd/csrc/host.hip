@@ -426,9 +426,11 @@ struct guess_ctx {
     double eps_rel = 1e-6;
     guess_op_t op = nullptr;
     hipStream_t stream = nullptr;
-    // extrapolation ring
+    // extrapolation ring: `slots` physical slots for M logical ones; an FP64
+    // ring keeps one spare, the slot the next update writes, which the guess
+    // never reads (so a caller may form the guess into it and solve in place)
     void *ring = nullptr;
-    int count = 0, head = 0;
+    int count = 0, head = 0, slots = 1;
     double beta[GUESS_MAX_M + 1][GUESS_MAX_M][GUESS_MAX_M] = {};  // [k][m][i]
     bool have_beta[GUESS_MAX_M + 1][GUESS_MAX_M] = {};
     // projection
@@ -471,8 +473,9 @@ static int ctx_buffers(int64_t N, int M, int method, int dtype, size_t sizes[6])
     const int es = esize(dtype);
     if (N < 1 || M < 1 || es == 0) return 0;
     const size_t col = (size_t)col_stride(N) * es;
-    if (method == GUESS_LAST) sizes[0] = col;
-    else if (ring_method(method)) sizes[0] = col * M;
+    const int spare = dtype == GUESS_F64 ? 1 : 0;
+    if (method == GUESS_LAST) sizes[0] = col * (1 + spare);
+    else if (ring_method(method)) sizes[0] = col * (M + spare);
     else if (proj_method(method)) {
         sizes[1] = col * M;
         sizes[2] = col * M;
@@ -579,7 +582,8 @@ extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
     };
     int rc = GUESS_OK;
     if (ring_method(g->method)) {
-        rc = alloc(&g->ring, col * g->M);
+        g->slots = g->M + (g->dtype == GUESS_F64 ? 1 : 0);
+        rc = alloc(&g->ring, col * g->slots);
     } else if (proj_method(g->method)) {
         rc = alloc(&g->X, col * g->M);
         if (rc == GUESS_OK) rc = alloc(&g->B, col * g->M);
@@ -678,10 +682,10 @@ extern "C" int guess_form(guess_t g, const double *b, double *x0) {
             const void *slots[GUESS_MAX_M];
             double w[GUESS_MAX_M];
             int nz = 0;
-            const int oldest = ((g->head - k) % g->M + g->M) % g->M;
+            const int oldest = ((g->head - k) % g->slots + g->slots) % g->slots;
             for (int j = 0; j < k; ++j) {
                 if (g->method == GUESS_SPEXTRAP && beta[j] == 0.0) continue;
-                slots[nz] = (const char *)g->ring + (size_t)((oldest + j) % g->M) * g->ld * g->es;
+                slots[nz] = (const char *)g->ring + (size_t)((oldest + j) % g->slots) * g->ld * g->es;
                 w[nz++] = beta[j];
             }
             LG_TRY(lg::launch_extrap_form(g->dtype, nz, slots, w, x0, N, g->stream, g->prof ? &g->kev : nullptr));
@@ -714,11 +718,15 @@ extern "C" int guess_update(guess_t g, const double *x, const double *Ax) {
         case GUESS_EXTRAP:
         case GUESS_SPEXTRAP: {
             void *slot = (char *)g->ring + (size_t)g->head * g->ld * g->es;
-            LG_TRY(lg::launch_ring_store(g->dtype, x, slot, N, g->stream, g->prof ? &g->kev : nullptr));
-            g->head = (g->head + 1) % g->M;
+            // a solution computed in the spare slot itself is already stored (§4: no copy
+            // when the solver works in place)
+            const bool in_place = (const void *)x == slot;
+            if (!in_place)
+                LG_TRY(lg::launch_ring_store(g->dtype, x, slot, N, g->stream, g->prof ? &g->kev : nullptr));
+            g->head = (g->head + 1) % g->slots;
             if (g->count < g->M) ++g->count;
-            g->update_bytes = (double)N * (8 + g->es);
-            return check_launch("guess_update");
+            g->update_bytes = in_place ? 0.0 : (double)N * (8 + g->es);
+            return in_place ? GUESS_OK : check_launch("guess_update");
         }
         case GUESS_PROJ:
         case GUESS_PROJ_QR: {
@@ -732,6 +740,15 @@ extern "C" int guess_update(guess_t g, const double *x, const double *Ax) {
         }
     }
     return fail(GUESS_EINVAL, "guess_update: bad method");
+}
+
+extern "C" int guess_next_slot(guess_t g, double **slot) {
+    if (!g || !slot) return fail(GUESS_EINVAL, "guess_next_slot: NULL argument");
+    *slot = nullptr;
+    if (!ring_method(g->method) || g->dtype != GUESS_F64)
+        return fail(GUESS_EINVAL, "guess_next_slot: needs an extrapolation context with FP64 history");
+    *slot = (double *)((char *)g->ring + (size_t)g->head * g->ld * g->es);
+    return GUESS_OK;
 }
 
 extern "C" int guess_get_info(guess_t g, guess_info *info) {
@@ -840,8 +857,8 @@ extern "C" int guess_history_get(guess_t g, int which, int j, double *out) {
     if (!g || !out) return fail(GUESS_EINVAL, "guess_history_get: NULL argument");
     if (ring_method(g->method)) {
         if (j < 0 || j >= g->count) return fail(GUESS_EINVAL, "guess_history_get: index out of range");
-        const int oldest = ((g->head - g->count) % g->M + g->M) % g->M;
-        const void *src = (const char *)g->ring + (size_t)((oldest + j) % g->M) * g->ld * g->es;
+        const int oldest = ((g->head - g->count) % g->slots + g->slots) % g->slots;
+        const void *src = (const char *)g->ring + (size_t)((oldest + j) % g->slots) * g->ld * g->es;
         LG_TRY(lg::launch_widen(g->dtype, src, 1.0, out, g->N, g->stream));
     } else if (proj_method(g->method)) {
         LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));

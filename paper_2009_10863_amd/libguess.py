@@ -72,6 +72,7 @@ def _load():
         "guess_op_destroy": (None, [P]),
         "guess_op_set_stream": (I, [P, P]),
         "guess_op_size": (I64, [P]),
+        "guess_next_slot": (I, [P, C.POINTER(C.c_void_p)]),
         "op_apply": (I, [P, P, P]),
         "pcg_solve": (I, [P, P, P, D, I, C.POINTER(I), C.POINTER(D)]),
         "pcg_solve_ex": (I, [P, P, P, D, I, I, C.POINTER(I), C.POINTER(D)]),
@@ -112,7 +113,7 @@ EXPORTED = (
     "pcg_solve", "pcg_solve_ex", "guess_create", "guess_create_ex", "guess_destroy",
     "guess_set_stream", "guess_set_op", "guess_workspace_bytes", "guess_form", "guess_update",
     "guess_get_info", "guess_reset", "guess_extrap_weights", "guess_spextrap_weights", "guess_history_get",
-    "guess_proj_factor",
+    "guess_proj_factor", "guess_next_slot",
     "workload_plane_wave_rhs", "workload_gaussian_rhs", "vec_multidot", "vec_combine", "guess_strerror",
     "guess_last_error", "guess_copy_kernel", "guess_profile", "guess_kernel_times",
 )
@@ -254,6 +255,13 @@ def guess_form(g, b, x0) -> None:
 def guess_update(g, x, Ax=None) -> None:
     n = _sizes.get(g)
     _check(_lib.guess_update(g, addr(x, n, "x"), addr(Ax, n, "Ax")))
+
+
+def guess_next_slot(g) -> int:
+    """Device address of the ring slot the next update writes (FP64 extrapolation contexts)."""
+    out = C.c_void_p()
+    _check(_lib.guess_next_slot(g, C.byref(out)))
+    return out.value
 
 
 def guess_get_info(g) -> dict:

@@ -54,16 +54,37 @@ class Operator:
 
 class GuessSequence:
     """Initial-guess history for one sequence of solves (one field).  eps_rel <= 0 selects the
-    library's rejection threshold for the storage format (1e-6 for FP64)."""
+    library's rejection threshold for the storage format (1e-6 for FP64).
+
+    in_place (FP64 extrapolation only): the context lives in a torch-owned workspace and
+    ``slot()`` is a view of the ring slot the next update writes; forming the guess into it,
+    solving there and updating with it stores the solution without a copy."""
 
     def __init__(self, N: int, M: int = 8, method: str = "extrap", degree: int = 2,
-                 dtype: str = "f64", eps_rel: float = 0.0, op: Operator = None, stream=None):
+                 dtype: str = "f64", eps_rel: float = 0.0, op: Operator = None, stream=None,
+                 in_place: bool = False):
         self.N, self.M, self.method, self.degree, self.dtype = N, M, method, degree, dtype
         self.op = op
         self.stream = L.stream_handle(stream)
         meth, inner = L.parse_method(method)
+        self.ws = None
+        if in_place:
+            if dtype != "f64" or method not in ("extrap", "spextrap", "last"):
+                raise ValueError("in_place needs an FP64 extrapolation context")
+            need = L.guess_workspace_bytes(N, M, meth, L.DTYPES[dtype])
+            self.ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+            off = (-self.ws.data_ptr()) % 256
+            self.ws = self.ws[off:off + need]
         self.handle = L.guess_create_ex(N, M, meth, degree, L.DTYPES[dtype], eps_rel,
-                                        op.handle if op is not None else None, self.stream, inner)
+                                        op.handle if op is not None else None, self.stream, inner,
+                                        workspace=self.ws)
+
+    def slot(self) -> torch.Tensor:
+        """View of the ring slot the next update writes (in_place contexts)."""
+        if self.ws is None:
+            raise ValueError("slot() needs a context made with in_place=True")
+        off = L.guess_next_slot(self.handle) - self.ws.data_ptr()
+        return self.ws[off:off + 8 * self.N].view(torch.float64)
 
     def form(self, b: torch.Tensor = None, out: torch.Tensor = None) -> torch.Tensor:
         out = _dev_f64(self.N, b.device if b is not None else "cuda") if out is None else out

@@ -46,7 +46,7 @@ def test_f64_guesses_match_oracle(lib, N):
     announce(f"extrap f64 N={N}")
     M, m = 8, 2
     res, info = _seq(lib, N, M, m, "f64", 12, seed=N)
-    assert info["count"] == M and info["head"] == 12 % M
+    assert info["count"] == M and info["head"] == 12 % (M + 1)   # FP64 rings keep a spare slot
     for q, (got, want, _) in enumerate(res):
         if q == 0:
             assert not got.any()
@@ -171,3 +171,42 @@ def test_reset_and_zero_guess(lib):
     finally:
         L.guess_destroy(g)
         L.guess_destroy(z)
+
+
+@pytest.mark.parametrize("method", ["extrap", "spextrap", "last"])
+def test_in_place_sequence_matches_copy(lib, method):
+    """Solving in the ring's spare slot (guess_next_slot): the same guesses, solutions and PCG
+    counts as the copying update, bit for bit, and the update moves nothing."""
+    import torch
+
+    from paper_2009_10863_amd.sequence import GuessSequence, Operator, PlaneWaveRHS
+
+    announce(f"in-place {method}")
+    L = lib
+    n, M, T = 16, 6, 12
+    op = Operator(n)
+    rhs = PlaneWaveRHS(synth.plane_wave_params(2, 4), n)
+    gc = GuessSequence(op.N, M, method, 2, "f64", 0.0, op)
+    gi = GuessSequence(op.N, M, method, 2, "f64", 0.0, op, in_place=True)
+    b = torch.empty(op.N, dtype=torch.float64, device="cuda")
+    xc = torch.empty_like(b)
+    try:
+        for k in range(1, T + 1):
+            rhs(0.01 * k, b)
+            gc.form(b, xc)
+            xi = gi.slot()
+            gi.form(b, xi)
+            assert torch.equal(xc, xi), k
+            s1 = op.solve(b, xc, 1e-10)
+            s2 = op.solve(b, xi, 1e-10)
+            assert s1[0] == s2[0] == L.OK and s1[1] == s2[1], k
+            assert torch.equal(xc, xi), k
+            gc.update(xc)
+            gi.update(xi)
+            assert gi.info()["update_bytes"] == 0.0 and gc.info()["update_bytes"] > 0.0
+        for j in range(gc.info()["count"]):
+            assert torch.equal(gc.history(j), gi.history(j)), j
+    finally:
+        gc.close()
+        gi.close()
+        op.close()
