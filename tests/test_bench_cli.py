@@ -32,3 +32,19 @@ def test_byte_model_closed_forms():
     assert sum(bench.kernel_bytes("projqr", "update", N, s, M, M, False)) == N * (7 * M * s + 40)
     # variable coefficient: the fused apply also reads the face arrays
     assert bench.kernel_bytes("proj", "update", N, s, 5, M, False, faces=123)[0] == N * (16 + 5 * s) + 123
+
+
+def test_mode_flags_parse(monkeypatch):
+    """The measurement modes and their options are accepted (they run only on a GPU)."""
+    for argv, check in (
+        (["--isolated", "--shard-nz", "32"], lambda a: a.isolated and a.shard_nz == 32),
+        (["--adjoint", "--adjoint-n", "64", "--adjoint-steps", "10"],
+         lambda a: a.adjoint and a.adjoint_n == 64 and a.adjoint_steps == 10),
+        (["--concurrent", "--n", "64"], lambda a: a.concurrent and a.n == 64),
+        (["--no-small-sequence", "--no-cpu-baseline"], lambda a: not a.small and not a.cpu),
+        (["--fields", "ins", "--rhs", "gaussian", "--stop-rule", "initresid"],
+         lambda a: a.fields == "ins" and a.rhs == "gaussian" and a.stop_rule == "initresid"),
+        ([], lambda a: a.eps_rel == 0.0 and a.small and a.cpu and a.steps == 20 and a.warmup == 10),
+    ):
+        monkeypatch.setattr(sys, "argv", ["bench.py"] + argv)
+        assert check(bench.parse()), argv
