@@ -18,7 +18,7 @@
  *     applies A once and runs twice-iterated classical Gram-Schmidt.
  *
  * around a matrix-free 7-point Helmholtz / variable-coefficient operator
- * and a Jacobi-preconditioned CG (§5.3) that judges the guesses.
+ * and a Jacobi-preconditioned CG (§5.3) that measures the guesses by the iterations they save.
  *
  * Conventions (every entry point):
  *   - Vectors are FP64, length N, on the device of the calling thread's
