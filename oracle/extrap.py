@@ -130,13 +130,19 @@ class ExtrapHistory:
     ``oracle.lowprec``); the guess itself is always evaluated in FP64 from the
     stored (rounded) values, which is the exact value the GPU's FP32
     accumulation approximates.
+
+    FP16 storage (a reading; the paper fixes no precision): a solution x is
+    stored as round(2^e x) with e = lowprec.f16_scale_exp(max |x|), so the
+    stored magnitudes lie below 2^15 whatever the size of the solution; the
+    value it stands for is 2^-e round(2^e x).  Other formats store round(x).
     """
 
     def __init__(self, M: int, m: int, dtype: str = "f64", sparse: bool = False):
         if not (0 <= m <= M - 1):
             raise ValueError("need 0 <= m <= M-1")
         self.M, self.m, self.dtype, self.sparse = M, m, dtype, sparse
-        self.hist = []          # oldest first, stored values as float64 arrays
+        self.hist = []          # oldest first, stored values (descaled) as float64 arrays
+        self.exps = []          # power-of-two exponent of each stored solution (FP16; else 0)
         self._cache = {}
 
     def weights(self, k: int):
@@ -157,14 +163,19 @@ class ExtrapHistory:
         return form(self.hist, self.weights(k))
 
     def update(self, x) -> None:
-        from .lowprec import round_store
+        from .lowprec import f16_scale_exp, round_store
 
-        self.hist.append(round_store(np.asarray(x, dtype=np.float64), self.dtype))
+        x = np.asarray(x, dtype=np.float64)
+        e = f16_scale_exp(float(np.max(np.abs(x)))) if self.dtype == "f16" and x.size else 0
+        self.hist.append(round_store(x, self.dtype, e))
+        self.exps.append(e)
         if len(self.hist) > self.M:
             self.hist.pop(0)
+            self.exps.pop(0)
 
     def reset(self) -> None:
         self.hist = []
+        self.exps = []
 
 
 # ---------------------------------------------------------------- sparse extrapolation (§3.3)

@@ -76,10 +76,16 @@ def f16_scale_exp(maxabs: float) -> int:
     """Power-of-two exponent e with maxabs * 2^e in [2^14, 2^15).
 
     Used for FP16 storage so that the largest stored magnitude sits well
-    inside the FP16 normal range (max 65504, min normal 2^-14).  Zero or
-    non-finite maxabs gives e = 0.
+    inside the FP16 normal range (max 65504, min normal 2^-14) and no stored
+    value of that vector can overflow.  Zero or non-finite maxabs gives e = 0;
+    e is clamped to [-100, 100] (beyond that the data are far outside any
+    range a solution of these systems takes), which keeps 2^-e times an
+    extrapolation weight a normal FP32 number.
     """
     if not np.isfinite(maxabs) or maxabs <= 0.0:
         return 0
     _, E = np.frexp(maxabs)          # maxabs = f 2^E, f in [0.5, 1)
-    return int(15 - E)
+    return int(min(max(15 - E, -F16_EXP_CLAMP), F16_EXP_CLAMP))
+
+
+F16_EXP_CLAMP = 100

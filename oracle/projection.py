@@ -33,11 +33,36 @@ that zeroes the subdiagonal entry b below the diagonal entry a has
 c = |a| / r, s = sign(a) b / r, r = sqrt(a^2 + b^2), with sign(0) = +1, so
 the new diagonal entry is sign(a) r (the listing's formulas for the rotation
 are read this way).
+
+Storage (the paper fixes no precision; this reading says which numbers are
+rounded to the storage format).  Column j is held as a stored pair S_j, T_j
+(arrays of the storage format) and one FP64 scale sigma_j; the true columns
+are X_j = sigma_j S_j and B_j = sigma_j T_j.
+
+* A new pair (x, b) of norm nu -- the raw solution at a restart, the
+  twice-orthogonalised remainder otherwise -- is stored as
+  S = round(2^e x), T = round(2^e b), sigma = 1 / (nu 2^e).  In exact
+  arithmetic sigma S = x / nu: the normalised column of the algorithm's update
+  step; only the rounding is placed on the unnormalised remainder.
+* e = 0 for FP64, FP32 and BF16.  FP16 has too narrow a range for raw
+  solutions and remainders, so there e is chosen from the pair's largest
+  magnitude m (lowprec.f16_scale_exp: m 2^e in [2^14, 2^15)), with m taken
+  from the raw pair at a restart and from the pair after the first
+  Gram-Schmidt pass otherwise (the second pass changes it only by rounding).
+* Rolling drop: within one update the rotated columns are exact FP64 vectors
+  (the new solution is orthogonalised against them); they are rounded when
+  the update stores them.  A rotated column keeps its slot's scale, except in
+  FP16, where slot i gets sigma'_i = 2^-15 (|c_i| t_i + |s_i| mu_{i+1}) with
+  t_0 = mu_0, t_{i+1} = |s_i| t_i + |c_i| mu_{i+1} and mu_j the largest true
+  magnitude of stored pair j: a bound on the rotated pair's largest
+  magnitude, so no stored value exceeds 2^15.
 Otherwise the steps are those of Algorithms 1 and 2 in order.
 """
 from __future__ import annotations
 
 import numpy as np
+
+from .lowprec import f16_scale_exp, round_store
 
 
 class Projection:
@@ -53,11 +78,14 @@ class Projection:
         self.last_accepted = None
         self.last_nu = None
         self.last_nu0 = None
+        self.last_exp = 0
 
     # ------------------------------------------------------------ state
     def reset(self) -> None:
-        self.X = []          # solution history
-        self.B = []          # B = A X
+        self.S = []          # stored columns of X (values of the storage format)
+        self.T = []          # stored columns of B = A X
+        self.sig = []        # FP64 scale of each stored pair: X_j = sig_j S_j, B_j = sig_j T_j
+        self.mu = []         # largest true magnitude of each stored pair (X_j and B_j together)
         self.raw = []        # raw solutions of the window: raw = X R
         self.R = np.zeros((0, 0))
         self.ratios = []     # nu / nu0 of every column accepted since the last reset / restart
@@ -65,7 +93,17 @@ class Projection:
 
     @property
     def d(self) -> int:
-        return len(self.X)
+        return len(self.S)
+
+    @property
+    def X(self):
+        """True columns of the solution history."""
+        return [sg * v for sg, v in zip(self.sig, self.S)]
+
+    @property
+    def B(self):
+        """True columns of B = A X."""
+        return [sg * v for sg, v in zip(self.sig, self.T)]
 
     @property
     def amplification(self) -> float:
@@ -78,17 +116,32 @@ class Projection:
         """
         return max([1.0] + [1.0 / r for r in self.ratios])
 
-    def _ip(self, x, b, j):
-        """Inner product of column j of the history with the pair (x, b = A x)."""
-        return float(self.X[j] @ b) if self.inner == "A" else float(self.B[j] @ b)
+    def _ip(self, xj, bj, b):
+        """Inner product of the column pair (xj, bj) with the pair (x, b = A x)."""
+        return float(xj @ b) if self.inner == "A" else float(bj @ b)
 
     def _norm2(self, x, b):
         return float(x @ b) if self.inner == "A" else float(b @ b)
 
-    def _store(self, v):
-        from .lowprec import round_store
+    def _exp_for(self, x, b) -> int:
+        """Power-of-two exponent of a new pair: 0, or for FP16 from its largest magnitude."""
+        if self.dtype != "f16":
+            return 0
+        return f16_scale_exp(max(float(np.max(np.abs(x))), float(np.max(np.abs(b)))))
 
-        return round_store(v, self.dtype)
+    def _put(self, x, b, sig):
+        """Append the stored pair round(x / sig), round(b / sig) with scale sig; x / sig and
+        b / sig are the caller's exact FP64 vectors in stored units."""
+        S = round_store(x, self.dtype)
+        T = round_store(b, self.dtype)
+        self.S.append(S)
+        self.T.append(T)
+        self.sig.append(sig)
+        self.mu.append(sig * max(float(np.max(np.abs(S))), float(np.max(np.abs(T)))))
+
+    def _put_new(self, x, b, nu, e):
+        """New column of norm nu: S = round(2^e x), T = round(2^e b), sigma = 1 / (nu 2^e)."""
+        self._put(np.ldexp(x, e), np.ldexp(b, e), 1.0 / float(np.ldexp(nu, e)))
 
     # ------------------------------------------------------------ guess
     def form(self, b) -> np.ndarray:
@@ -96,19 +149,24 @@ class Projection:
         b = np.asarray(b, dtype=np.float64)
         if self.d == 0:
             return np.zeros_like(b)
-        alpha = [float(xj @ b) for xj in self.X] if self.inner == "A" else [float(bj @ b) for bj in self.B]
-        x0 = alpha[0] * self.X[0]
-        for a, xj in zip(alpha[1:], self.X[1:]):
+        X = self.X
+        alpha = [float(xj @ b) for xj in X] if self.inner == "A" else [float(bj @ b) for bj in self.B]
+        x0 = alpha[0] * X[0]
+        for a, xj in zip(alpha[1:], X[1:]):
             x0 = x0 + a * xj
         return x0
 
     # ------------------------------------------------------------ update
     def _drop_oldest(self):
         """Algorithm 2, QR update: delete the first column of R, restore triangular
-        form with Givens rotations of rows i, i+1, rotate the columns of X and B."""
+        form with Givens rotations of rows i, i+1, rotate the columns of X and B.
+
+        Updates R and the raw window; returns the d-1 rotated true columns of X
+        and of B (exact FP64 vectors) and the rotations (c_i, s_i)."""
         d = self.d
         R = self.R[:, 1:].copy()                 # d x (d-1), upper Hessenberg
-        X, B = list(self.X), list(self.B)
+        X, B = self.X, self.B
+        rots = []
         for i in range(d - 1):
             a, b = R[i, i], R[i + 1, i]
             r = float(np.hypot(a, b))
@@ -120,17 +178,28 @@ class Projection:
             R[i, i], R[i + 1, i] = sg * r, 0.0        # the entries the rotation fixes by construction
             X[i], X[i + 1] = c * X[i] + s * X[i + 1], -s * X[i] + c * X[i + 1]
             B[i], B[i + 1] = c * B[i] + s * B[i + 1], -s * B[i] + c * B[i + 1]
+            rots.append((c, s))
         self.R = R[: d - 1, :]
-        self.X = [self._store(v) for v in X[: d - 1]]
-        self.B = [self._store(v) for v in B[: d - 1]]
         self.raw = self.raw[1:]
         self.drops += 1
+        return X[: d - 1], B[: d - 1], rots
 
-    def _add_first(self, x, xt, bt, nu0):
+    def _rotated_scales(self, rots):
+        """Scale of each slot after a rolling drop (see the module docstring)."""
+        if self.dtype != "f16":
+            return list(self.sig[: len(rots)])
+        out, t = [], self.mu[0]
+        for i, (c, s) in enumerate(rots):
+            out.append(float(np.ldexp(abs(c) * t + abs(s) * self.mu[i + 1], -15)))
+            t = abs(s) * t + abs(c) * self.mu[i + 1]
+        return out
+
+    def _restart(self, x, xt, bt, nu0):
         ok = bool(np.isfinite(nu0) and nu0 > 0.0)
+        self.last_exp = 0
         if ok:
-            self.X.append(self._store(xt / nu0))
-            self.B.append(self._store(bt / nu0))
+            self.last_exp = self._exp_for(xt, bt)
+            self._put_new(xt, bt, nu0, self.last_exp)
             self.raw.append(np.array(x, dtype=np.float64, copy=True))
             self.R = np.array([[nu0]])
             self.ratios.append(1.0)
@@ -138,8 +207,13 @@ class Projection:
         self.last_accepted = ok
         return ok
 
-    def update(self, x, Ax=None) -> bool:
-        """Add the new solution to the history; returns whether it was accepted."""
+    def update(self, x, Ax=None, decide=None) -> bool:
+        """Add the new solution to the history; returns whether it was accepted.
+
+        ``decide`` (True / False) replaces the rejection test by a given
+        decision: a replay that compares two implementations forces the other
+        side's decision where nu / nu0 sits within rounding of eps_rel.
+        """
         xt = np.array(x, dtype=np.float64, copy=True)
         bt = self.apply_A(xt) if Ax is None else np.array(Ax, dtype=np.float64, copy=True)
         s0 = self._norm2(xt, bt)
@@ -148,27 +222,41 @@ class Projection:
         if self.variant == "classic":
             if self.d == 0 or self.d >= self.M:
                 self.reset()
-                return self._add_first(x, xt, bt, nu0)
+                return self._restart(x, xt, bt, nu0)
+            Xc, Bc, keep = self.X, self.B, None
         else:
+            keep = None
             if self.d == self.M:
-                self._drop_oldest()
-            if self.d == 0:
-                return self._add_first(x, xt, bt, nu0)
-        d = self.d
+                Xc, Bc, rots = self._drop_oldest()
+                keep = (Xc, Bc, self._rotated_scales(rots))
+                self.S, self.T, self.sig, self.mu = [], [], [], []
+            else:
+                Xc, Bc = self.X, self.B
+            if len(Xc) == 0:
+                return self._restart(x, xt, bt, nu0)
+        d = len(Xc)
         ctot = np.zeros(d)
-        for _ in range(2):
-            c = [self._ip(xt, bt, j) for j in range(d)]
-            for cj, xj, bj in zip(c, self.X, self.B):
+        e = 0
+        for p in range(2):
+            c = [self._ip(xj, bj, bt) for xj, bj in zip(Xc, Bc)]
+            for cj, xj, bj in zip(c, Xc, Bc):
                 bt = bt - cj * bj
                 xt = xt - cj * xj
             ctot += np.array(c)
+            if p == 0:
+                e = self._exp_for(xt, bt)
         s = self._norm2(xt, bt)
         nu = float(np.sqrt(s)) if s >= 0 else float("nan")
         self.last_nu = nu
-        ok = bool(np.isfinite(nu) and nu > self.eps_rel * nu0)
+        self.last_exp = e
+        fin = bool(np.isfinite(nu))
+        ok = fin and (nu > self.eps_rel * nu0 if decide is None else bool(decide))
+        if keep is not None:
+            # the rotated columns are stored (rounded) at the end of the update
+            for xj, bj, sg in zip(*keep):
+                self._put(xj / sg, bj / sg, sg)
         if ok:
-            self.X.append(self._store(xt / nu))
-            self.B.append(self._store(bt / nu))
+            self._put_new(xt, bt, nu, e)
             self.raw.append(np.array(x, dtype=np.float64, copy=True))
             R = np.zeros((d + 1, d + 1))
             R[:d, :d] = self.R

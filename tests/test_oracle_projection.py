@@ -185,8 +185,7 @@ def test_pins_catch_planted_mistakes(monkeypatch):
                 bt = bt - cj * bj
                 xt = xt + cj * xj          # planted: wrong sign
         nu = np.sqrt(abs(xt @ bt))
-        self.X.append(xt / nu)
-        self.B.append(bt / nu)
+        self._put_new(xt, bt, nu, 0)
         self.raw.append(np.array(x, dtype=float))
         return True
 

@@ -160,8 +160,9 @@ def test_pins_catch_planted_mistakes(monkeypatch):
     good = Projection._drop_oldest
 
     def drop_newest(self):           # drops the newest instead of the oldest
-        self.X, self.B, self.raw = self.X[:-1], self.B[:-1], self.raw[1:]
+        self.raw = self.raw[1:]
         self.R = self.R[:-1, :-1]
+        return self.X[:-1], self.B[:-1], [(1.0, 0.0)] * (self.d - 1)
     monkeypatch.setattr(Projection, "_drop_oldest", drop_newest)
     assert not pins_hold()
 
@@ -178,7 +179,8 @@ def test_pins_catch_planted_mistakes(monkeypatch):
             R[i + 1, i] = 0.0
             X[i], X[i + 1] = c * X[i] + s * X[i + 1], -s * X[i] + c * X[i + 1]
             B[i], B[i + 1] = c * B[i] + s * B[i + 1], -s * B[i] + c * B[i + 1]
-        self.R, self.X, self.B, self.raw = R[: d - 1], X[: d - 1], B[: d - 1], self.raw[1:]
+        self.R, self.raw = R[: d - 1], self.raw[1:]
+        return X[: d - 1], B[: d - 1], [(1.0, 0.0)] * (d - 1)
     monkeypatch.setattr(Projection, "_drop_oldest", no_sign)
     assert not pins_hold()
 
@@ -194,7 +196,8 @@ def test_pins_catch_planted_mistakes(monkeypatch):
             R[i + 1, i] = 0.0
             X[i], X[i + 1] = c * X[i] - s * X[i + 1], s * X[i] + c * X[i + 1]
             B[i], B[i + 1] = c * B[i] - s * B[i + 1], s * B[i] + c * B[i + 1]
-        self.R, self.X, self.B, self.raw = R[: d - 1], X[: d - 1], B[: d - 1], self.raw[1:]
+        self.R, self.raw = R[: d - 1], self.raw[1:]
+        return X[: d - 1], B[: d - 1], [(1.0, 0.0)] * (d - 1)
     monkeypatch.setattr(Projection, "_drop_oldest", transposed_rotation)
     assert not pins_hold()
 
@@ -207,7 +210,8 @@ def test_pins_catch_planted_mistakes(monkeypatch):
             c, s = abs(a) / r, np.sign(a) * bb / r
             R[i:i + 2, :] = np.array([[c, s], [-s, c]]) @ R[i:i + 2, :]
             R[i + 1, i] = 0.0
-        self.R, self.X, self.B, self.raw = R[: d - 1], self.X[1:], self.B[1:], self.raw[1:]
+        self.R, self.raw = R[: d - 1], self.raw[1:]
+        return self.X[1:], self.B[1:], [(1.0, 0.0)] * (d - 1)
     monkeypatch.setattr(Projection, "_drop_oldest", columns_not_rotated)
     assert not pins_hold()
     monkeypatch.setattr(Projection, "_drop_oldest", good)
