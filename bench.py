@@ -44,23 +44,42 @@ KERNELS = {
 for _m in ("projqr", "proj_l2", "projqr_l2"):
     KERNELS[(_m, "form")] = KERNELS[("proj", "form")]
     KERNELS[(_m, "update")] = KERNELS[("proj", "update")]
+RING = ("extrap", "last", "spextrap")
 
 
-def kernel_bytes(method, call, N, s, k_or_d, M, restart, faces=0):
+def kernel_names(method, call, dtype="f64"):
+    """Kernels of one call in launch order; an FP16 ring store is followed by the kernel that
+    stores the slot again when the solution's exponent differs from the previous one's."""
+    if method in RING and call == "update" and dtype == "f16":
+        return ["ring_store", "ring_fix"]
+    return KERNELS[(method, call)]
+
+
+def kernel_bytes(method, call, N, s, k_or_d, M, restart, faces=0, dtype="f64", fixed=False):
     """Algorithmic HBM bytes of each kernel of one call (list, launch order).
 
     `faces`: bytes of the operator's face arrays, read by the fused operator
-    apply of a variable-coefficient workload."""
-    if method in ("extrap", "last", "spextrap"):
+    apply of a variable-coefficient workload.  `fixed`: an FP16 ring store that
+    had to store the slot again (the ring_fix kernel moved the same bytes)."""
+    f16 = dtype == "f16"
+    if method in RING:
         if call == "form":
             return [N * (k_or_d * s + 8)] if k_or_d > 0 else []
+        if f16:
+            return [N * (8 + s), N * (8 + s) if fixed else 0]
         return [N * (8 + s)]
     d = k_or_d
     if call == "form":
         return [N * (d * s + 8) if d > 0 else 0, 0, N * (d * s + 8)]
+    if restart and f16:
+        # the apply pass reads x and writes A x with max |x|, |A x|; the write kernel stores the pair
+        return [N * 16 + faces, 0, 0, 0, N * (16 + 2 * s), 0]
     if restart:
         return [N * (8 + 2 * s) + faces, 0, 0, 0, 0, 0]
-    reorth = N * ((1 if method.endswith("_l2") else 2) * d * s + 8)
+    if f16:
+        reorth = N * (2 * d * s + 16)      # also forms x - X c1 for the pair's exponent
+    else:
+        reorth = N * ((1 if method.endswith("_l2") else 2) * d * s + 8)
     if method.startswith("projqr") and d == M:      # rolling drop: every column rotated in place
         return [N * (16 + d * s) + faces, 0, reorth, 0, N * (4 * d * s + 16), 0]
     return [N * (16 + d * s) + faces, 0, reorth, 0, N * (2 * d * s + 16 + 2 * s), 0]
@@ -296,7 +315,7 @@ def isolated(args, L):
             tf.append(L.guess_kernel_times(g)[0])
             evict()
             L.guess_update(g, b)
-            tu.append(L.guess_kernel_times(g)[0])
+            tu.append(sum(L.guess_kernel_times(g)))   # FP16: store + exponent check (same exponent: no re-store)
         out[f"extrap_form_{dt}"] = N * (M * s + 8) / (med(tf) * 1e-3) / 1e9
         out[f"ring_store_{dt}"] = N * (8 + s) / (med(tu) * 1e-3) / 1e9
         us[f"extrap_form_{dt}"] = med(tf) * 1e3
@@ -635,6 +654,9 @@ def main():
             inf1 = L.guess_get_info(g)
             L.guess_update(g, x)
             tu = L.guess_kernel_times(g)
+            fixed = False
+            if dtype == "f16" and m in RING and timed:
+                fixed = L.guess_get_info(g)["update_bytes"] > 1.5 * N * (8 + s)
             if shadow:
                 L.guess_update(sh[fi, m], x)
             if st != L.OK:
@@ -653,8 +675,8 @@ def main():
             else:
                 restart = m.startswith("proj") and (dd == 0 or dd >= M)
             for call, times, kdd in (("form", tf, kd_form), ("update", tu, inf1["count"])):
-                names = KERNELS[(m, call)]
-                byts = kernel_bytes(m, call, N, s, kdd, M, restart, faces)
+                names = kernel_names(m, call, dtype)
+                byts = kernel_bytes(m, call, N, s, kdd, M, restart, faces, dtype, fixed)
                 for name, ms, by in zip(names, times, byts):
                     # every kernel of the call counts in the guess time; the
                     # per-kernel table keeps the streaming kernels that moved data

@@ -89,7 +89,11 @@ enum {
 /* ------------------------------------------------------------------ operator */
 
 /*
- * Create the operator A on an nx x ny x nz grid of interior nodes:
+ * The operator replaces the paper's spectral-element discretisation of §5
+ * (whose mesh and solver are not part of the guess method): a 7-point
+ * finite-difference Helmholtz / variable-coefficient operator, symmetric
+ * positive definite, so every guess method and the PCG of §5.3 apply as
+ * stated.  Create the operator A on an nx x ny x nz grid of interior nodes:
  *   kappa == NULL:  (Au)_i = inv_h2 (6 u_i - sum_nb u_nb) + shift u_i
  *   kappa != NULL:  (Au)_i = inv_h2 sum_faces k_f (u_i - u_nb) + shift u_i,
  *                   k_f = 2 k_i k_nb / (k_i + k_nb),
@@ -109,7 +113,9 @@ int guess_op_set_stream(guess_op_t A, void *stream);
 /* Number of unknowns nx*ny*nz. */
 int64_t guess_op_size(guess_op_t A);
 
-/* y = A x.  x and y must not alias. */
+/* y = A x (the operator above, evaluated in the fixed order stated there).
+ * x and y are device vectors of guess_op_size(A) doubles, 16-byte aligned,
+ * and must not alias (EINVAL).  Enqueued on the operator's stream. */
 int op_apply(guess_op_t A, const double *x, double *y);
 
 /*
@@ -152,8 +158,18 @@ typedef struct guess_opts {
 /*
  * Create a context with FP64 history, eps_rel = 1e-6, no operator, the null
  * stream.  LAST forces M = 1.  Returns NULL on failure (see guess_last_error).
+ * The history bound M is the paper's M (§2, Algorithms 1 and 2; §3.2, the M
+ * solutions the extrapolation fits), the degree its m (§3.2).  The rejection
+ * threshold reads the paper's absolute epsilon of §2 (which depends on the
+ * solver's stopping criterion) as relative: a new solution is kept iff its
+ * A-norm after Gram-Schmidt exceeds eps_rel times its A-norm before, so the
+ * test does not depend on the scale of the solutions.
  */
 guess_t guess_create(int64_t N, int M, int method, int degree);
+/* As guess_create with every option of guess_opts (storage format, eps_rel,
+ * operator, stream, inner product, caller workspace).  *out receives the
+ * context, or NULL with a status: EINVAL for a bad option (the checks are
+ * listed with guess_opts), ENOMEM when a device allocation fails. */
 int guess_create_ex(const guess_opts *o, guess_t *out);
 void guess_destroy(guess_t g);
 int guess_set_stream(guess_t g, void *stream);
@@ -180,14 +196,18 @@ size_t guess_workspace_bytes(int64_t N, int M, int method, int dtype);
 int guess_form(guess_t g, const double *b, double *x0);
 
 /*
- * Add the solution x of the latest solve to the history.
+ * Add the solution x of the latest solve to the history (§2: the update of
+ * Algorithms 1 and 2; §3.2: the extrapolation keeps the last M solutions).
+ * x (and Ax) are device vectors of N doubles, 16-byte aligned, owned by the
+ * caller and only read.
  *   EXTRAP / LAST: x is rounded to the storage format into the next ring slot;
  *     when x is that slot (guess_next_slot) nothing is copied.
  *   PROJ: Ax = A x if the caller has it (Ax = b is allowed, then
  *     X^T A X = I holds only to the solve tolerance); Ax == NULL makes the
  *     library apply the bound operator once (EINVAL if none is bound).
- *     Restart when the history is empty or full (slot 1 <- x / ||x||_A);
- *     otherwise two classical Gram-Schmidt passes in the A inner product,
+ *     Restart when the history is empty or full (slot 1 <- x / ||x||_A;
+ *     Algorithm 1's restart step); otherwise two classical Gram-Schmidt
+ *     passes in the A inner product (Algorithm 1's orthogonalisation),
  *     then the new pair is kept iff nu > eps_rel * nu0 (nu, nu0 the A-norms
  *     after / before orthogonalisation).  The decision is taken on the
  *     device; a non-finite nu rejects the vector and sets a sticky flag.
@@ -258,9 +278,25 @@ int guess_extrap_weights(int m, int k, double *beta);
 int guess_spextrap_weights(int m, int k, double *beta);
 
 /* Copy stored history vector j (PROJ: column j of X (which = 0) or B
- * (which = 1), scale applied; EXTRAP: j-th oldest stored solution) into
- * the FP64 device vector out.  For tests and checkpoints; synchronises. */
+ * (which = 1), scale applied; EXTRAP: j-th oldest stored solution, FP16
+ * slots descaled) into the FP64 device vector out.  For tests and
+ * checkpoints; synchronises. */
 int guess_history_get(guess_t g, int which, int j, double *out);
+
+/*
+ * The same vector as the storage format holds it: out receives the stored
+ * values widened to FP64 without any scale, *scale (host) the FP64 factor
+ * that turns them into the true values.  Reduced-precision storage (the
+ * paper fixes no precision; the reading is the library's): a projection
+ * column is the stored pair round(2^e x''), round(2^e b'') with scale
+ * 1 / (nu 2^e) -- in exact arithmetic the normalised column of §2's update
+ * step -- e = 0 except for FP16, where max |stored| lies in [2^14, 2^15);
+ * an FP16 extrapolation slot holds round(2^e x) with scale 2^-e; other
+ * slots have scale 1.  Same indices and errors as guess_history_get
+ * (GUESS_EINVAL for an index out of range or a method without history);
+ * out is a device vector of N doubles owned by the caller.  Synchronises.
+ */
+int guess_history_raw(guess_t g, int which, int j, double *out, double *scale);
 
 /*
  * PROJ, PROJ_QR: the triangular factor of the history, raw solutions = X R

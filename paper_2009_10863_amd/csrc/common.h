@@ -200,32 +200,43 @@ __device__ __forceinline__ double wave_max(double v) {
 // LDS scratch that a kernel passes to the reduction helpers below.
 constexpr int kLdsDoubles = kWaves * kMaxDots + kMaxDots;
 
-// Sum ND per-thread values over the workgroup; thread j < ND of the block
-// writes the block's total of value j to part[blockIdx.x * ND + j].
+// Largest of two magnitudes, NaN-propagating (a NaN anywhere gives NaN).
+__device__ __forceinline__ double nanmax(double a, double b) { return (a != a || a > b) ? a : b; }
+__device__ __forceinline__ double wave_nanmax(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Reduce ND per-thread values over the workgroup -- values j < NS by sum,
+// the others (magnitudes) by NaN-propagating max; thread j < ND of the
+// block writes the block's result for value j to part[blockIdx.x * ND + j].
 // The order of additions is fixed, so results do not depend on timing.
-template <int ND>
+template <int ND, int NS = ND>
 __device__ __forceinline__ void block_partials(const double (&v)[ND], double *part, double *lds) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < ND; ++j) {
-        double s = wave_sum(v[j]);
+        double s = j < NS ? wave_sum(v[j]) : wave_nanmax(v[j]);
         if (lane == 0) lds[wave * ND + j] = s;
     }
     __syncthreads();
     if (threadIdx.x < ND) {
+        const bool sum = (int)threadIdx.x < NS;
         double s = lds[threadIdx.x];
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w) s += lds[w * ND + threadIdx.x];
+        for (int w = 1; w < kWaves; ++w) s = sum ? s + lds[w * ND + threadIdx.x] : nanmax(s, lds[w * ND + threadIdx.x]);
         part[(int64_t)blockIdx.x * ND + threadIdx.x] = s;
     }
     __syncthreads();
 }
 
-// Total of value j over nb partial rows (written by an earlier kernel),
-// summed in a fixed order (thread t takes rows t, t+256, ...; then a fixed
-// tree), so every workgroup that calls it obtains identical totals.  Every
-// thread of the workgroup receives all ND totals.
-template <int ND>
+// Result for value j over nb partial rows (written by an earlier kernel),
+// summed (j < NS) or max-reduced (j >= NS) in a fixed order (thread t takes
+// rows t, t+256, ...; then a fixed tree), so every workgroup that calls it
+// obtains identical totals.  Every thread of the workgroup receives all ND
+// results.
+template <int ND, int NS = ND>
 __device__ __forceinline__ void final_sums(const double *part, int nb, double (&tot)[ND],
                                            double *lds) {
     double v[ND];
@@ -234,26 +245,48 @@ __device__ __forceinline__ void final_sums(const double *part, int nb, double (&
     for (int r = threadIdx.x; r < nb; r += kBlock) {
         const double *row = part + (int64_t)r * ND;
 #pragma unroll
-        for (int j = 0; j < ND; ++j) v[j] += __builtin_nontemporal_load(row + j);
+        for (int j = 0; j < ND; ++j) {
+            const double x = __builtin_nontemporal_load(row + j);
+            v[j] = j < NS ? v[j] + x : nanmax(v[j], x);
+        }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int j = 0; j < ND; ++j) {
-        double s = wave_sum(v[j]);
+        double s = j < NS ? wave_sum(v[j]) : wave_nanmax(v[j]);
         if (lane == 0) lds[wave * ND + j] = s;
     }
     __syncthreads();
     double *out = lds + kWaves * kMaxDots;
     if (threadIdx.x < ND) {
+        const bool sum = (int)threadIdx.x < NS;
         double s = lds[threadIdx.x];
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w) s += lds[w * ND + threadIdx.x];
+        for (int w = 1; w < kWaves; ++w) s = sum ? s + lds[w * ND + threadIdx.x] : nanmax(s, lds[w * ND + threadIdx.x]);
         out[threadIdx.x] = s;
     }
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < ND; ++j) tot[j] = out[j];
 }
+
+// Power-of-two exponent e that brings a largest magnitude m into
+// [2^14, 2^15) (FP16 storage: the stored values of a vector then stay well
+// inside FP16's normal range and cannot overflow).  m = f 2^E, f in
+// [0.5, 1), gives e = 15 - E, clamped to [-100, 100]; zero or non-finite m
+// gives 0.
+constexpr int kF16ExpClamp = 100;
+__host__ __device__ __forceinline__ int f16_scale_exp(double m) {
+    if (!(m > 0.0) || !(m <= 1.7976931348623157e308)) return 0;
+    int E = 0;
+    (void)frexp(m, &E);
+    int e = 15 - E;
+    return e < -kF16ExpClamp ? -kF16ExpClamp : (e > kF16ExpClamp ? kF16ExpClamp : e);
+}
+
+// Value an FP64 magnitude takes once stored in FP16 (two-step rounding),
+// widened back to FP64.
+__device__ __forceinline__ double f16_rounded(double v) { return to_f64<GUESS_F16>(to_store<GUESS_F16>(v)); }
 
 // Call f(std::integral_constant<int, D>) for the runtime value d in [LO, HI].
 template <int LO, int HI, class F>

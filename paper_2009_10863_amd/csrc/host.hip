@@ -431,6 +431,8 @@ struct guess_ctx {
     // never reads (so a caller may form the guess into it and solve in place)
     void *ring = nullptr;
     int count = 0, head = 0, slots = 1;
+    lg::RingState *rs = nullptr, *host_rs = nullptr;   // FP16 ring: per-slot exponents (device)
+    int gen = 0;                                         // FP16 ring: stores so far, mod 2
     double beta[GUESS_MAX_M + 1][GUESS_MAX_M][GUESS_MAX_M] = {};  // [k][m][i]
     bool have_beta[GUESS_MAX_M + 1][GUESS_MAX_M] = {};
     // projection
@@ -453,9 +455,10 @@ static void ctx_free(guess_ctx *g) {
             (void)hipEventDestroy(g->kev.stop[i]);
         }
     if (!g->external)
-        for (void *ptr : {g->ring, g->X, g->B, (void *)g->w, (void *)g->part, (void *)g->st})
+        for (void *ptr : {g->ring, g->X, g->B, (void *)g->w, (void *)g->part, (void *)g->st, (void *)g->rs})
             if (ptr) (void)hipFree(ptr);
     if (g->host_st) (void)hipHostFree(g->host_st);
+    if (g->host_rs) (void)hipHostFree(g->host_rs);
     delete g;
 }
 
@@ -469,13 +472,14 @@ static bool proj_method(int method) { return method == GUESS_PROJ || method == G
 static size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 
 static int ctx_buffers(int64_t N, int M, int method, int dtype, size_t sizes[6]) {
-    for (int i = 0; i < 6; ++i) sizes[i] = 0;   // ring, X, B, w, part, st
+    for (int i = 0; i < 6; ++i) sizes[i] = 0;   // ring, X, B, w, part, state
     const int es = esize(dtype);
     if (N < 1 || M < 1 || es == 0) return 0;
     const size_t col = (size_t)col_stride(N) * es;
     const int spare = dtype == GUESS_F64 ? 1 : 0;
     if (method == GUESS_LAST) sizes[0] = col * (1 + spare);
     else if (ring_method(method)) sizes[0] = col * (M + spare);
+    if (ring_method(method) && dtype == GUESS_F16) sizes[5] = round256(sizeof(lg::RingState));
     else if (proj_method(method)) {
         sizes[1] = col * M;
         sizes[2] = col * M;
@@ -493,6 +497,20 @@ extern "C" size_t guess_workspace_bytes(int64_t N, int M, int method, int dtype)
     size_t t = 0;
     for (size_t b : sizes) t += b;
     return t;
+}
+
+// FP16 ring: every exponent 0, both max accumulators clear.
+static int ring_upload_state(guess_ctx *g) {
+    *g->host_rs = lg::RingState{};
+    LG_HIP(hipMemcpyAsync(g->rs, g->host_rs, sizeof(lg::RingState), hipMemcpyHostToDevice, g->stream));
+    LG_HIP(hipStreamSynchronize(g->stream));
+    return GUESS_OK;
+}
+
+static int ring_read_state(guess_ctx *g) {
+    LG_HIP(hipMemcpyAsync(g->host_rs, g->rs, sizeof(lg::RingState), hipMemcpyDeviceToHost, g->stream));
+    LG_HIP(hipStreamSynchronize(g->stream));
+    return GUESS_OK;
 }
 
 static int proj_upload_state(guess_ctx *g) {
@@ -584,6 +602,12 @@ extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
     if (ring_method(g->method)) {
         g->slots = g->M + (g->dtype == GUESS_F64 ? 1 : 0);
         rc = alloc(&g->ring, col * g->slots);
+        if (rc == GUESS_OK && g->dtype == GUESS_F16) {
+            rc = alloc((void **)&g->rs, sizeof(lg::RingState));
+            if (rc == GUESS_OK && hipHostMalloc((void **)&g->host_rs, sizeof(lg::RingState), hipHostMallocDefault) != hipSuccess)
+                rc = fail(GUESS_ENOMEM, "guess_create: pinned allocation failed");
+            if (rc == GUESS_OK) rc = ring_upload_state(g);
+        }
     } else if (proj_method(g->method)) {
         rc = alloc(&g->X, col * g->M);
         if (rc == GUESS_OK) rc = alloc(&g->B, col * g->M);
@@ -681,14 +705,17 @@ extern "C" int guess_form(guess_t g, const double *b, double *x0) {
             // for least-squares weights, m+1 for the sparse scheme)
             const void *slots[GUESS_MAX_M];
             double w[GUESS_MAX_M];
+            int sidx[GUESS_MAX_M];
             int nz = 0;
             const int oldest = ((g->head - k) % g->slots + g->slots) % g->slots;
             for (int j = 0; j < k; ++j) {
                 if (g->method == GUESS_SPEXTRAP && beta[j] == 0.0) continue;
-                slots[nz] = (const char *)g->ring + (size_t)((oldest + j) % g->slots) * g->ld * g->es;
+                sidx[nz] = (oldest + j) % g->slots;
+                slots[nz] = (const char *)g->ring + (size_t)sidx[nz] * g->ld * g->es;
                 w[nz++] = beta[j];
             }
-            LG_TRY(lg::launch_extrap_form(g->dtype, nz, slots, w, x0, N, g->stream, g->prof ? &g->kev : nullptr));
+            LG_TRY(lg::launch_extrap_form(g->dtype, nz, slots, w, x0, N, g->stream, g->prof ? &g->kev : nullptr,
+                                          g->rs, sidx));
             g->form_bytes = (double)N * (nz * g->es + 8);
             return check_launch("guess_form");
         }
@@ -721,8 +748,11 @@ extern "C" int guess_update(guess_t g, const double *x, const double *Ax) {
             // a solution computed in the spare slot itself is already stored (§4: no copy
             // when the solver works in place)
             const bool in_place = (const void *)x == slot;
-            if (!in_place)
-                LG_TRY(lg::launch_ring_store(g->dtype, x, slot, N, g->stream, g->prof ? &g->kev : nullptr));
+            if (!in_place) {
+                LG_TRY(lg::launch_ring_store(g->dtype, x, slot, N, g->stream, g->prof ? &g->kev : nullptr, g->rs,
+                                             g->head, g->gen));
+                g->gen ^= 1;
+            }
             g->head = (g->head + 1) % g->slots;
             if (g->count < g->M) ++g->count;
             g->update_bytes = in_place ? 0.0 : (double)N * (8 + g->es);
@@ -778,12 +808,16 @@ extern "C" int guess_get_info(guess_t g, guess_info *info) {
         const double N = (double)g->N, es = g->es;
         if (g->form_bytes < 0) info->form_bytes = 2.0 * N * (s.form_d * es + 8.0) - (s.form_d == 0 ? N * 8.0 : 0.0);
         if (g->update_bytes < 0) {
-            // apply 16 + d s; reorth 2 d s + 8 (l2: d s + 8); write 2 d s + 16 + 2 s,
-            // or with a rolling drop 4 d s + 16; restart 8 (+8) + 2 s
+            // apply 16 + d s; reorth 2 d s + 8 (l2: d s + 8; FP16, either: 2 d s + 16, as it
+            // also forms x - X c1 for the exponent); write 2 d s + 16 + 2 s, or with a
+            // rolling drop 4 d s + 16; restart 8 (+8) + 2 s, FP16 16 + 16 + 2 s (the apply
+            // pass writes A x, or reads the caller's, and the write kernel stores the pair)
             const int d = s.upd_d;
+            const bool f16 = g->dtype == GUESS_F16;
             const bool restart = d == 0 || (g->method == GUESS_PROJ_QR ? g->M == 1 : d >= g->M);
-            const double reorth = (g->inner == GUESS_INNER_L2 ? 1.0 : 2.0) * d * es + 8.0;
-            if (restart) info->update_bytes = N * (8.0 + 2.0 * es + (g->last_update_ax ? 8.0 : 0.0));
+            const double reorth = f16 ? 2.0 * d * es + 16.0 : (g->inner == GUESS_INNER_L2 ? 1.0 : 2.0) * d * es + 8.0;
+            if (restart && f16) info->update_bytes = N * (32.0 + 2.0 * es);
+            else if (restart) info->update_bytes = N * (8.0 + 2.0 * es + (g->last_update_ax ? 8.0 : 0.0));
             else if (s.drop) info->update_bytes = N * (16.0 + d * es + reorth + 4.0 * d * es + 16.0);
             else info->update_bytes = N * (16.0 + d * es + reorth + 2.0 * d * es + 16.0 + 2.0 * es);
             // a variable-coefficient operator applied by the library also reads its face arrays
@@ -797,6 +831,11 @@ extern "C" int guess_get_info(guess_t g, guess_info *info) {
         LG_HIP(hipStreamSynchronize(g->stream));
         info->count = g->count;
         info->head = g->head;
+        // an FP16 store that had to be repeated with this solution's exponent moved its bytes twice
+        if (g->rs && g->update_bytes > 0.0) {
+            LG_TRY(ring_read_state(g));
+            if (g->host_rs->last_fixed) info->update_bytes = 2.0 * g->update_bytes;
+        }
     }
     return GUESS_OK;
 }
@@ -853,25 +892,48 @@ extern "C" int guess_kernel_times(guess_t g, double *ms, int max, int *n) {
     return GUESS_OK;
 }
 
-extern "C" int guess_history_get(guess_t g, int which, int j, double *out) {
-    if (!g || !out) return fail(GUESS_EINVAL, "guess_history_get: NULL argument");
+// Stored vector j and its FP64 scale (true values = scale * stored values).
+static int history_vector(guess_t g, int which, int j, const char *fn, const void **src, double *scale) {
     if (ring_method(g->method)) {
-        if (j < 0 || j >= g->count) return fail(GUESS_EINVAL, "guess_history_get: index out of range");
-        const int oldest = ((g->head - g->count) % g->slots + g->slots) % g->slots;
-        const void *src = (const char *)g->ring + (size_t)((oldest + j) % g->slots) * g->ld * g->es;
-        LG_TRY(lg::launch_widen(g->dtype, src, 1.0, out, g->N, g->stream));
-    } else if (proj_method(g->method)) {
+        if (j < 0 || j >= g->count) return fail(GUESS_EINVAL, std::string(fn) + ": index out of range");
+        const int slot = ((g->head - g->count) % g->slots + g->slots + j) % g->slots;
+        *src = (const char *)g->ring + (size_t)slot * g->ld * g->es;
+        *scale = 1.0;
+        if (g->rs) {
+            LG_TRY(ring_read_state(g));
+            *scale = std::ldexp(1.0, -g->host_rs->exps[slot]);
+        }
+        return GUESS_OK;
+    }
+    if (proj_method(g->method)) {
         LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));
         LG_HIP(hipStreamSynchronize(g->stream));
         if (j < 0 || j >= g->host_st->d || (which != 0 && which != 1))
-            return fail(GUESS_EINVAL, "guess_history_get: index out of range");
-        const void *base = which == 0 ? g->X : g->B;
-        const void *src = (const char *)base + (size_t)j * g->ld * g->es;
-        LG_TRY(lg::launch_widen(g->dtype, src, g->host_st->scale[j], out, g->N, g->stream));
-    } else {
-        return fail(GUESS_EINVAL, "guess_history_get: no history for this method");
+            return fail(GUESS_EINVAL, std::string(fn) + ": index out of range");
+        *src = (const char *)(which == 0 ? g->X : g->B) + (size_t)j * g->ld * g->es;
+        *scale = g->host_st->scale[j];
+        return GUESS_OK;
     }
+    return fail(GUESS_EINVAL, std::string(fn) + ": no history for this method");
+}
+
+extern "C" int guess_history_get(guess_t g, int which, int j, double *out) {
+    if (!g || !out) return fail(GUESS_EINVAL, "guess_history_get: NULL argument");
+    const void *src = nullptr;
+    double scale = 1.0;
+    LG_TRY(history_vector(g, which, j, "guess_history_get", &src, &scale));
+    LG_TRY(lg::launch_widen(g->dtype, src, scale, out, g->N, g->stream));
     LG_TRY(check_launch("guess_history_get"));
+    LG_HIP(hipStreamSynchronize(g->stream));
+    return GUESS_OK;
+}
+
+extern "C" int guess_history_raw(guess_t g, int which, int j, double *out, double *scale) {
+    if (!g || !out || !scale) return fail(GUESS_EINVAL, "guess_history_raw: NULL argument");
+    const void *src = nullptr;
+    LG_TRY(history_vector(g, which, j, "guess_history_raw", &src, scale));
+    LG_TRY(lg::launch_widen(g->dtype, src, 1.0, out, g->N, g->stream));
+    LG_TRY(check_launch("guess_history_raw"));
     LG_HIP(hipStreamSynchronize(g->stream));
     return GUESS_OK;
 }

@@ -54,6 +54,23 @@ struct ProjState {
     double R[GUESS_MAX_M][GUESS_MAX_M];  // raw solutions of the history = X R (upper triangular)
     double gc[GUESS_MAX_M], gs[GUESS_MAX_M];  // rolling drop: Givens rotations (c, s)
     double rot[GUESS_MAX_M][4];  // rolling drop: the rotations in stored units, per slot
+    // FP16 storage only:
+    double mu[GUESS_MAX_M];      // largest true magnitude of stored pair j (X_j and B_j together)
+    double nscale[GUESS_MAX_M];  // rolling drop: scale of each rotated slot, committed by the update's end
+};
+
+// Device-resident state of an FP16 extrapolation ring: every slot holds
+// round(2^e x) with its own exponent e (from max |x|).  A store first tries
+// the exponent of the previous store, reduces max |x| alongside, and a
+// second kernel re-stores the slot only when the exponent differs.
+struct RingState {
+    unsigned long long maxbits[2];  // bits of max |x| of the store in flight (two, alternating)
+    int e_used[2];                  // exponent each in-flight store was written with
+    int e_guess;                    // exponent the next store tries
+    int last_fixed;                 // the last update re-stored its slot
+    int fixes;                      // re-stores so far
+    int pad;
+    int exps[GUESS_MAX_M + 1];      // exponent of each physical slot
 };
 
 // Device-resident state of a PCG solve (rho of iteration k in rho[k & 1]).
@@ -68,9 +85,10 @@ struct PcgState {
 
 // ---- extrapolation (extrap.hip)
 int launch_extrap_form(int dtype, int k, const void *const *slots, const double *beta,
-                       double *x0, int64_t N, hipStream_t s, KEvents *ev = nullptr);
+                       double *x0, int64_t N, hipStream_t s, KEvents *ev = nullptr,
+                       const RingState *rs = nullptr, const int *slot_index = nullptr);
 int launch_ring_store(int dtype, const double *x, void *slot, int64_t N, hipStream_t s,
-                      KEvents *ev = nullptr);
+                      KEvents *ev = nullptr, RingState *rs = nullptr, int slot_index = 0, int gen = 0);
 int launch_fill_zero(double *x, int64_t N, hipStream_t s);
 int launch_widen(int dtype, const void *src, double scale, double *out, int64_t N, hipStream_t s);
 

@@ -93,6 +93,18 @@ __device__ __forceinline__ const void *dot_cols(const ProjArgs &a) {
     return (VF & VF_L2) ? a.B : a.X;
 }
 
+// FP16 storage has a narrow range, so a new FP16 pair (x, b) is stored
+// multiplied by 2^e with max(|x|, |b|) 2^e in [2^14, 2^15): the magnitudes of
+// the raw pair at a restart, of the pair after the first Gram-Schmidt pass
+// otherwise (reduced alongside that pass; the second pass changes them only
+// by rounding).  Wider formats store the pair as it is (e = 0).  Either way
+// the column's FP64 scale is 1 / (nu 2^e).
+template <int DT>
+constexpr bool scaled_store() {
+    return DT == GUESS_F16;
+}
+__device__ __forceinline__ double absmax2(double a, double b) { return nanmax(fabs(a), fabs(b)); }
+
 // ------------------------------------------------------------------ form
 template <int DT, int VF>
 LG_REDUCE_KERNEL void proj_dots_kernel(ProjArgs a, const double *__restrict__ b) {
@@ -186,24 +198,40 @@ LG_REDUCE_KERNEL void proj_apply_kernel(ProjArgs a, Grid g, const double *__rest
         else return apply_pt<VAR>(VecU{x}, g, i);
     };
     if (proj_restart<VF>(d, a.M)) {
-        // restart: slot 1 <- x, B slot 1 <- A x; partial nu0^2 = x^T A x (l2: |A x|^2)
-        double acc[1] = {0.0};
+        // restart: slot 1 <- x, B slot 1 <- A x; partial nu0^2 = x^T A x (l2: |A x|^2).
+        // FP16: the exponent of the stored pair needs max(|x|, |A x|) first, so this pass
+        // writes w = A x and reduces the max; the Gram-Schmidt write kernel stores the pair.
+        constexpr bool SC = scaled_store<DT>();
+        double acc[SC ? 2 : 1];
+#pragma unroll
+        for (int j = 0; j < (SC ? 2 : 1); ++j) acc[j] = 0.0;
         for (int64_t c = cr.begin; c < cr.end; c += cr.step) {
             V4 xv;
             const V4 wv = xw4(c, xv);
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[0]);
-            store4<DT>(a.Xw, c, xv);
-            store4<DT>(a.Bw, c, wv);
+            if constexpr (SC) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[SC ? 1 : 0] = nanmax(acc[SC ? 1 : 0], absmax2(xv.v[e], wv.v[e]));
+                if constexpr (!HAVE_AX) store4<GUESS_F64>(a.w, c, wv);
+            } else {
+                store4<DT>(a.Xw, c, xv);
+                store4<DT>(a.Bw, c, wv);
+            }
         }
         if (blockIdx.x == 0 && threadIdx.x < rem) {
             const int64_t i = tail_start(a.N) + threadIdx.x;
             const double wv = xw1(i);
             acc[0] = __builtin_fma(L2 ? wv : x[i], wv, acc[0]);
-            store1<DT>(a.Xw, i, x[i]);
-            store1<DT>(a.Bw, i, wv);
+            if constexpr (SC) {
+                acc[SC ? 1 : 0] = nanmax(acc[SC ? 1 : 0], absmax2(x[i], wv));
+                if constexpr (!HAVE_AX) a.w[i] = wv;
+            } else {
+                store1<DT>(a.Xw, i, x[i]);
+                store1<DT>(a.Bw, i, wv);
+            }
         }
-        block_partials<1>(acc, a.part, lds);
+        block_partials<SC ? 2 : 1, 1>(acc, a.part, lds);
         return;
     }
     const void *C = dot_cols<VF>(a);
@@ -247,16 +275,25 @@ LG_REDUCE_KERNEL void proj_apply_march_kernel(ProjArgs a, Grid g, March m, const
     constexpr bool L2 = (VF & VF_L2) != 0;
     const int d = a.st->d;
     if (proj_restart<VF>(d, a.M)) {
-        double acc[1] = {0.0};
+        constexpr bool SC = scaled_store<DT>();
+        double acc[SC ? 2 : 1];
+#pragma unroll
+        for (int j = 0; j < (SC ? 2 : 1); ++j) acc[j] = 0.0;
         march_sweep<VAR>(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &pa, const R2 &pb, const R4 &au) {
             const V4 xv{{pa.v[0], pa.v[1], pb.v[0], pb.v[1]}};
             const V4 wv{{au.v[0], au.v[1], au.v[2], au.v[3]}};
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[0]);
-            store4<DT>(a.Xw, c, xv);
-            store4<DT>(a.Bw, c, wv);
+            if constexpr (SC) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) acc[SC ? 1 : 0] = nanmax(acc[SC ? 1 : 0], absmax2(xv.v[e], wv.v[e]));
+                store4<GUESS_F64>(a.w, c, wv);
+            } else {
+                store4<DT>(a.Xw, c, xv);
+                store4<DT>(a.Bw, c, wv);
+            }
         });
-        block_partials<1>(acc, a.part, lds);
+        block_partials<SC ? 2 : 1, 1>(acc, a.part, lds);
         return;
     }
     const void *C = dot_cols<VF>(a);
@@ -284,20 +321,12 @@ LG_REDUCE_KERNEL void proj_apply_march_kernel(ProjArgs a, Grid g, March m, const
     });
 }
 
-// FP16 storage has a narrow range, so each new FP16 column is stored
-// multiplied by a power of two chosen from its norm after the first
-// Gram-Schmidt pass (computed here as one more partial sum; the A-form
-// also reads x for it).  Wider formats store the column as it is.
-template <int DT>
-constexpr bool scaled_store() {
-    return DT == GUESS_F16;
-}
-
 template <int DT, int VF>
 LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ x, const double *__restrict__ w) {
     __shared__ double lds[kLdsDoubles];
     constexpr bool L2 = (VF & VF_L2) != 0;
-    constexpr bool EST = scaled_store<DT>();
+    constexpr bool EST = scaled_store<DT>();   // also reduce max(|x'|, |w'|), x' = x - X c1
+    constexpr bool NEEDX = !L2 || EST;
     if (a.st->mode != 0) return;
     const int d = a.st->d;
     const int64_t nc = nchunks(a.N), stride = (int64_t)gridDim.x * kBlock;
@@ -310,10 +339,10 @@ LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ 
 #pragma unroll
         for (int j = 0; j < ND; ++j) acc[j] = 0.0;
         for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
-            V4 bc[D], xc[L2 ? 1 : D];
+            V4 bc[D], xc[NEEDX ? D : 1];
 #pragma unroll
             for (int j = 0; j < D; ++j) bc[j] = load4<DT>(colp<DT>(a.B, a.ld, j), c);
-            if constexpr (!L2) {
+            if constexpr (NEEDX) {
 #pragma unroll
                 for (int j = 0; j < D; ++j) xc[j] = load4<DT>(colp<DT>(a.X, a.ld, j), c);
             }
@@ -326,20 +355,15 @@ LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ 
             for (int j = 0; j < D; ++j)
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    acc[j] = __builtin_fma(L2 ? bc[j].v[e] : xc[L2 ? 0 : j].v[e], wv.v[e], acc[j]);
+                    acc[j] = __builtin_fma(L2 ? bc[j].v[e] : xc[NEEDX ? j : 0].v[e], wv.v[e], acc[j]);
             if constexpr (EST) {
-                if constexpr (L2) {
+                V4 xv = load4<GUESS_F64>(x, c);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) acc[D] = __builtin_fma(wv.v[e], wv.v[e], acc[D]);
-                } else {
-                    V4 xv = load4<GUESS_F64>(x, c);
+                for (int j = 0; j < D; ++j)
 #pragma unroll
-                    for (int j = 0; j < D; ++j)
+                    for (int e = 0; e < 4; ++e) xv.v[e] = __builtin_fma(-cs[j], xc[NEEDX ? j : 0].v[e], xv.v[e]);
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) xv.v[e] = __builtin_fma(-cs[j], xc[j].v[e], xv.v[e]);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) acc[D] = __builtin_fma(xv.v[e], wv.v[e], acc[D]);
-                }
+                for (int e = 0; e < 4; ++e) acc[ND - 1] = nanmax(acc[ND - 1], absmax2(xv.v[e], wv.v[e]));
             }
         }
         if (blockIdx.x == 0 && threadIdx.x < tail_count(a.N)) {
@@ -348,24 +372,26 @@ LG_REDUCE_KERNEL void proj_reorth_kernel(ProjArgs a, const double *__restrict__ 
 #pragma unroll
             for (int j = 0; j < D; ++j) {
                 wv = __builtin_fma(-cs[j], load1<DT>(colp<DT>(a.B, a.ld, j), i), wv);
-                if constexpr (EST && !L2) xv = __builtin_fma(-cs[j], load1<DT>(colp<DT>(a.X, a.ld, j), i), xv);
+                if constexpr (EST) xv = __builtin_fma(-cs[j], load1<DT>(colp<DT>(a.X, a.ld, j), i), xv);
             }
 #pragma unroll
             for (int j = 0; j < D; ++j)
                 acc[j] = __builtin_fma(load1<DT>(colp<DT>(L2 ? a.B : a.X, a.ld, j), i), wv, acc[j]);
-            if constexpr (EST) acc[D] = __builtin_fma(L2 ? wv : xv, wv, acc[D]);
+            if constexpr (EST) acc[ND - 1] = nanmax(acc[ND - 1], absmax2(xv, wv));
         }
-        block_partials<ND>(acc, a.part, lds);
+        block_partials<ND, D>(acc, a.part, lds);
     });
 }
 
 // Rolling drop, one array (X or B) of one chunk: subtract the projection
 // from v, rotate the D old columns in place (slot i <- rotated column i,
 // i < D-1) and store v in slot D-1.  rot[i] = {a, b, e, f} in stored units:
-// new_i = a t_i + b S_{i+1}, t_{i+1} = e t_i + f S_{i+1}, t_0 = S_0.
-template <int DT, int D>
+// new_i = a t_i + b S_{i+1}, t_{i+1} = e t_i + f S_{i+1}, t_0 = S_0.  With MX
+// the magnitudes of the values written into slot i are max-reduced into mx[i]
+// (FP16: the rotated pairs' largest stored magnitudes).
+template <int DT, int D, bool MX>
 __device__ __forceinline__ void rotate_chunk(const void *S, void *Sw, int64_t ld, int64_t c, const double (&cs)[D],
-                                             const double (&rot)[D - 1][4], double pw, V4 &v) {
+                                             const double (&rot)[D - 1][4], double pw, V4 &v, double (&mx)[D]) {
     V4 col[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) col[j] = load4<DT>(colp<DT>(S, ld, j), c);
@@ -381,17 +407,21 @@ __device__ __forceinline__ void rotate_chunk(const void *S, void *Sw, int64_t ld
         for (int e = 0; e < 4; ++e) {
             nw.v[e] = __builtin_fma(rot[i][1], col[i + 1].v[e], rot[i][0] * t.v[e]);
             t.v[e] = __builtin_fma(rot[i][3], col[i + 1].v[e], rot[i][2] * t.v[e]);
+            if constexpr (MX) mx[i] = nanmax(mx[i], fabs(nw.v[e]));
         }
         store4<DT>(colw<DT>(Sw, ld, i), c, nw);
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) v.v[e] *= pw;
+    for (int e = 0; e < 4; ++e) {
+        v.v[e] *= pw;
+        if constexpr (MX) mx[D - 1] = nanmax(mx[D - 1], fabs(v.v[e]));
+    }
     store4<DT>(colw<DT>(Sw, ld, D - 1), c, v);
 }
 
-template <int DT, int D>
+template <int DT, int D, bool MX>
 __device__ __forceinline__ double rotate_one(const void *S, void *Sw, int64_t ld, int64_t i, const double (&cs)[D],
-                                             const double (&rot)[D - 1][4], double pw, double v) {
+                                             const double (&rot)[D - 1][4], double pw, double v, double (&mx)[D]) {
     double col[D];
 #pragma unroll
     for (int j = 0; j < D; ++j) col[j] = load1<DT>(colp<DT>(S, ld, j), i);
@@ -402,9 +432,11 @@ __device__ __forceinline__ double rotate_one(const void *S, void *Sw, int64_t ld
     for (int q = 0; q < D - 1; ++q) {
         const double nw = __builtin_fma(rot[q][1], col[q + 1], rot[q][0] * t);
         t = __builtin_fma(rot[q][3], col[q + 1], rot[q][2] * t);
+        if constexpr (MX) mx[q] = nanmax(mx[q], fabs(nw));
         store1<DT>(colw<DT>(Sw, ld, q), i, nw);
     }
     v *= pw;
+    if constexpr (MX) mx[D - 1] = nanmax(mx[D - 1], fabs(v));
     store1<DT>(colw<DT>(Sw, ld, D - 1), i, v);
     return v;
 }
@@ -414,9 +446,33 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
                                            const double *__restrict__ w) {
     __shared__ double lds[kLdsDoubles];
     constexpr bool L2 = (VF & VF_L2) != 0;
-    if (a.st->mode != 0) return;
-    const int d = a.st->d;
+    constexpr bool SC = scaled_store<DT>();
     const int64_t nc = nchunks(a.N), stride = (int64_t)gridDim.x * kBlock;
+    if (a.st->mode != 0) {
+        // FP16 restart: store the raw pair (x, A x) times the exponent found by the apply pass
+        if constexpr (SC) {
+            if (a.st->mode != 1 || a.st->d != 1) return;
+            const double pw = a.st->pow2;
+            for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
+                V4 xv = load4<GUESS_F64>(x, c);
+                V4 wv = load4<GUESS_F64>(w, c);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    xv.v[e] *= pw;
+                    wv.v[e] *= pw;
+                }
+                store4<DT>(a.Xw, c, xv);
+                store4<DT>(a.Bw, c, wv);
+            }
+            if (blockIdx.x == 0 && threadIdx.x < tail_count(a.N)) {
+                const int64_t i = tail_start(a.N) + threadIdx.x;
+                store1<DT>(a.Xw, i, x[i] * pw);
+                store1<DT>(a.Bw, i, w[i] * pw);
+            }
+        }
+        return;
+    }
+    const int d = a.st->d;
     if constexpr ((VF & VF_QR) != 0) {
         if (d == a.M) {
             dispatch_d<2, GUESS_MAX_M>(d, [&](auto Dc) {
@@ -428,23 +484,34 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
                 for (int i = 0; i < D - 1; ++i)
 #pragma unroll
                     for (int q = 0; q < 4; ++q) rot[i][q] = a.st->rot[i][q];
-                const double pw = scaled_store<DT>() ? a.st->pow2 : 1.0;
-                double acc[1] = {0.0};
+                const double pw = SC ? a.st->pow2 : 1.0;
+                // acc[0]: nu^2 of the new pair; FP16 also the largest stored magnitude of
+                // the new pair (acc[1]) and of rotated pair i (acc[2 + i])
+                double acc[SC ? D + 1 : 1], mx[D];
+#pragma unroll
+                for (int j = 0; j < (SC ? D + 1 : 1); ++j) acc[j] = 0.0;
+#pragma unroll
+                for (int j = 0; j < D; ++j) mx[j] = 0.0;
                 for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
                     V4 xv = load4<GUESS_F64>(x, c);
                     V4 wv = load4<GUESS_F64>(w, c);
-                    rotate_chunk<DT, D>(a.X, a.Xw, a.ld, c, cs, rot, pw, xv);
-                    rotate_chunk<DT, D>(a.B, a.Bw, a.ld, c, cs, rot, pw, wv);
+                    rotate_chunk<DT, D, SC>(a.X, a.Xw, a.ld, c, cs, rot, pw, xv, mx);
+                    rotate_chunk<DT, D, SC>(a.B, a.Bw, a.ld, c, cs, rot, pw, wv, mx);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[0]);
                 }
                 if (blockIdx.x == 0 && threadIdx.x < tail_count(a.N)) {
                     const int64_t i = tail_start(a.N) + threadIdx.x;
-                    const double xv = rotate_one<DT, D>(a.X, a.Xw, a.ld, i, cs, rot, pw, x[i]);
-                    const double wv = rotate_one<DT, D>(a.B, a.Bw, a.ld, i, cs, rot, pw, w[i]);
+                    const double xv = rotate_one<DT, D, SC>(a.X, a.Xw, a.ld, i, cs, rot, pw, x[i], mx);
+                    const double wv = rotate_one<DT, D, SC>(a.B, a.Bw, a.ld, i, cs, rot, pw, w[i], mx);
                     acc[0] = __builtin_fma(L2 ? wv : xv, wv, acc[0]);
                 }
-                block_partials<1>(acc, a.part, lds);
+                if constexpr (SC) {
+                    acc[SC ? 1 : 0] = mx[D - 1];
+#pragma unroll
+                    for (int i = 0; i < D - 1; ++i) acc[SC ? 2 + i : 0] = mx[i];
+                }
+                block_partials<SC ? D + 1 : 1, 1>(acc, a.part, lds);
             });
             return;
         }
@@ -456,8 +523,11 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
         for (int j = 0; j < D; ++j) cs[j] = a.st->cs[j];
         void *Xd = colw<DT>(a.Xw, a.ld, D);
         void *Bd = colw<DT>(a.Bw, a.ld, D);
-        const double pw = scaled_store<DT>() ? a.st->pow2 : 1.0;
-        double acc[1] = {0.0};
+        const double pw = SC ? a.st->pow2 : 1.0;
+        // acc[0]: nu^2 of the new pair; FP16 also its largest stored magnitude (acc[1])
+        double acc[SC ? 2 : 1];
+#pragma unroll
+        for (int j = 0; j < (SC ? 2 : 1); ++j) acc[j] = 0.0;
         for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
             V4 xc[D], bc[D];
 #pragma unroll
@@ -478,6 +548,7 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
                 xv.v[e] *= pw;
                 wv.v[e] *= pw;
                 acc[0] = __builtin_fma(L2 ? wv.v[e] : xv.v[e], wv.v[e], acc[0]);
+                if constexpr (SC) acc[SC ? 1 : 0] = nanmax(acc[SC ? 1 : 0], absmax2(xv.v[e], wv.v[e]));
             }
             store4<DT>(Xd, c, xv);
             store4<DT>(Bd, c, wv);
@@ -493,10 +564,11 @@ LG_REDUCE_KERNEL void proj_gs_write_kernel(ProjArgs a, const double *__restrict_
             xv *= pw;
             wv *= pw;
             acc[0] = __builtin_fma(L2 ? wv : xv, wv, acc[0]);
+            if constexpr (SC) acc[SC ? 1 : 0] = nanmax(acc[SC ? 1 : 0], absmax2(xv, wv));
             store1<DT>(Xd, i, xv);
             store1<DT>(Bd, i, wv);
         }
-        block_partials<1>(acc, a.part, lds);
+        block_partials<SC ? 2 : 1, 1>(acc, a.part, lds);
     });
 }
 
@@ -533,6 +605,14 @@ __device__ __forceinline__ void rot_backward(const double *gc, const double *gs,
 // Givens rotations that return R(:, 2:M) to triangular form, the rotated
 // factor (written back to st->R, last row and column cleared), and the
 // per-slot rotation coefficients in stored units for proj_gs_write.
+// A rotated slot keeps its scale, except in FP16, where slot i gets the
+// scale 2^-15 (|c_i| t_i + |s_i| mu_{i+1}) with t_0 = mu_0,
+// t_{i+1} = |s_i| t_i + |c_i| mu_{i+1} (mu_j the largest true magnitude of
+// stored pair j): a bound on the rotated pair's largest magnitude, so that
+// no stored value exceeds 2^15.  The new scales take effect at the end of
+// the update (proj_fin after proj_gs_write); until then the coefficients
+// of the update refer to the old stored columns.
+template <int DT>
 __device__ __forceinline__ void qr_drop_plan(ProjState *st, int M) {
     __shared__ double H[GUESS_MAX_M][GUESS_MAX_M + 1];
     __shared__ double gcl[GUESS_MAX_M], gsl[GUESS_MAX_M];
@@ -568,13 +648,58 @@ __device__ __forceinline__ void qr_drop_plan(ProjState *st, int M) {
         const int i = t / M, j = t % M;
         st->R[i][j] = (i < M - 1 && j < M - 1 && j >= i) ? H[i][j] : 0.0;
     }
+    __shared__ double nsc[GUESS_MAX_M];
+    if (t == 0) {
+        double tt = scaled_store<DT>() ? st->mu[0] : 0.0;
+        for (int i = 0; i < M - 1; ++i) {
+            if constexpr (scaled_store<DT>()) {
+                const double ac = fabs(gcl[i]), as = fabs(gsl[i]), mn = st->mu[i + 1];
+                nsc[i] = ldexp(ac * tt + as * mn, -15);
+                tt = as * tt + ac * mn;
+            } else {
+                nsc[i] = st->scale[i];
+            }
+            st->nscale[i] = nsc[i];
+        }
+    }
+    __syncthreads();
     if (t < M - 1) {
         const double c = gcl[t], s = gsl[t];
-        const double si = st->scale[t], sn = st->scale[t + 1];
-        st->rot[t][0] = c;
-        st->rot[t][1] = s * (sn / si);
+        const double si = st->scale[t], sn = st->scale[t + 1], sp = nsc[t];
+        st->rot[t][0] = c * (si / sp);
+        st->rot[t][1] = s * (sn / sp);
         st->rot[t][2] = -s * (si / sn);
         st->rot[t][3] = c;
+    }
+}
+
+// End of an update that orthogonalised a new pair (slot d, or d - 1 after a
+// rolling drop): nsq = nu^2 2^{2e} of the stored pair, mx its largest stored
+// magnitude before rounding (FP16).  Accept iff nu > eps_rel nu0; the new
+// column's scale is 1 / (nu 2^e) and column d of R holds its coefficients.
+template <int DT>
+__device__ __forceinline__ void gs_accept(ProjState *st, int d, bool drop, double nsq, double mx) {
+    const int slot = drop ? d - 1 : d;     // the new pair's column
+    const double pw = scaled_store<DT>() ? st->pow2 : 1.0;   // the pair was stored multiplied by pw
+    const double nu = sqrt(nsq) / pw;      // NaN when rounding made it negative
+    const bool fin = isfinite(nu);
+    const bool ok = fin && nu > st->eps_rel * st->nu0;
+    // new column of the factor: raw x = X c + nu x~
+    if (ok && (int)threadIdx.x < slot) st->R[threadIdx.x][slot] = st->c[threadIdx.x];
+    if (threadIdx.x == 0) {
+        st->nusq = nsq / (pw * pw);
+        st->nu = nu;
+        st->last_accepted = ok ? 1 : 0;
+        if (!fin) st->nonfinite = 1;
+        if (ok) {
+            st->scale[slot] = 1.0 / (nu * pw);
+            if constexpr (scaled_store<DT>()) st->mu[slot] = st->scale[slot] * f16_rounded(mx);
+            st->R[slot][slot] = nu;
+            st->d = slot + 1;
+        } else {
+            st->rejects += 1;
+            st->d = slot;
+        }
     }
 }
 
@@ -597,11 +722,15 @@ __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
         });
     } else if constexpr (KIND == FIN_APPLY) {
         if (proj_restart<VF>(d, a.M)) {
-            double tot[1];
-            final_sums<1>(a.part, nb, tot, lds);
+            constexpr bool SC = scaled_store<DT>();
+            double tot[SC ? 2 : 1];
+            final_sums<SC ? 2 : 1, 1>(a.part, nb, tot, lds);
             if (threadIdx.x == 0) {
                 const double nu0 = sqrt(tot[0]);
                 const bool ok = isfinite(nu0) && nu0 > 0.0;
+                // FP16: the raw pair is stored times 2^e (by proj_gs_write), e from max(|x|, |A x|)
+                const double pw = SC ? ldexp(1.0, f16_scale_exp(tot[SC ? 1 : 0])) : 1.0;
+                st->pow2 = pw;
                 st->upd_d = d;
                 st->nu0sq = tot[0];
                 st->nu0 = nu0;
@@ -612,14 +741,15 @@ __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
                 else st->restarts += 1;
                 st->last_accepted = ok ? 1 : 0;
                 if (!isfinite(nu0)) st->nonfinite = 1;
-                st->scale[0] = ok ? 1.0 / nu0 : 0.0;
+                st->scale[0] = ok ? 1.0 / (nu0 * pw) : 0.0;
+                if constexpr (SC) st->mu[0] = ok ? st->scale[0] * f16_rounded(tot[SC ? 1 : 0] * pw) : 0.0;
                 st->R[0][0] = ok ? nu0 : 0.0;
                 st->d = ok ? 1 : 0;
             }
             return;
         }
         const bool drop = (VF & VF_QR) != 0 && d == a.M;
-        if (drop) qr_drop_plan(st, a.M);
+        if (drop) qr_drop_plan<DT>(st, a.M);
         dispatch_d<1, gs_max<VF>()>(d, [&](auto Dc) {
             constexpr int D = decltype(Dc)::value;
             double tot[D + 1];
@@ -660,7 +790,7 @@ __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
             constexpr int D = decltype(Dc)::value;
             constexpr int ND = scaled_store<DT>() ? D + 1 : D;
             double tot[ND];
-            final_sums<ND>(a.part, nb, tot, lds);
+            final_sums<ND, D>(a.part, nb, tot, lds);
             if (drop) {
                 if constexpr (D >= 2) {
                     if (threadIdx.x == 0) {
@@ -684,47 +814,38 @@ __global__ __launch_bounds__(kBlock) void proj_fin_kernel(ProjArgs a, int nb) {
                 st->cs[threadIdx.x] = cj * sc;
             }
             if constexpr (scaled_store<DT>()) {
-                if (threadIdx.x == 0) {
-                    // store the new pair multiplied by the power of two that brings its
-                    // norm after the first pass, nu1, back to the raw solution's nu0
-                    // (exact): the stored values stay in the range of the raw solutions
-                    const double nu0 = st->nu0, nu1 = sqrt(tot[D]);
-                    double pw = 1.0;
-                    if (isfinite(nu0) && nu0 > 0.0 && isfinite(nu1) && nu1 > 0.0) {
-                        int ex = ilogb(nu0) - ilogb(nu1);
-                        ex = ex < 0 ? 0 : (ex > 60 ? 60 : ex);
-                        pw = ldexp(1.0, ex);
-                    }
-                    st->pow2 = pw;
-                }
+                // the new pair is stored times 2^e, e from its largest magnitude after the
+                // first Gram-Schmidt pass
+                if (threadIdx.x == 0) st->pow2 = ldexp(1.0, f16_scale_exp(tot[ND - 1]));
             }
         });
     } else {
         if (st->mode != 0 || d < 1 || d > a.M) return;
         const bool drop = (VF & VF_QR) != 0 && st->drop != 0;
         if (!drop && d >= a.M) return;
-        double tot[1];
-        final_sums<1>(a.part, nb, tot, lds);
-        const int slot = drop ? d - 1 : d;     // the new pair's column
-        const double pw = scaled_store<DT>() ? st->pow2 : 1.0;   // the pair was stored multiplied by pw
-        const double nu = sqrt(tot[0]) / pw;   // NaN when rounding made it negative
-        const bool fin = isfinite(nu);
-        const bool ok = fin && nu > st->eps_rel * st->nu0;
-        // new column of the factor: raw x = X c + nu x~
-        if (ok && threadIdx.x < slot) st->R[threadIdx.x][slot] = st->c[threadIdx.x];
-        if (threadIdx.x == 0) {
-            st->nusq = tot[0] / (pw * pw);
-            st->nu = nu;
-            st->last_accepted = ok ? 1 : 0;
-            if (!fin) st->nonfinite = 1;
-            if (ok) {
-                st->scale[slot] = 1.0 / (nu * pw);
-                st->R[slot][slot] = nu;
-                st->d = slot + 1;
-            } else {
-                st->rejects += 1;
-                st->d = slot;
+        if constexpr (scaled_store<DT>()) {
+            if ((VF & VF_QR) != 0 && drop) {
+                dispatch_d<2, GUESS_MAX_M>(d, [&](auto Dc) {
+                    constexpr int D = decltype(Dc)::value;
+                    double tot[D + 1];
+                    final_sums<D + 1, 1>(a.part, nb, tot, lds);
+                    gs_accept<DT>(st, d, true, tot[0], tot[1]);
+                    // the rotated slots take their new scales
+                    if (threadIdx.x < D - 1) {
+                        const double sp = st->nscale[threadIdx.x];
+                        st->scale[threadIdx.x] = sp;
+                        st->mu[threadIdx.x] = sp * f16_rounded(tot[2 + threadIdx.x]);
+                    }
+                });
+                return;
             }
+            double tot[2];
+            final_sums<2, 1>(a.part, nb, tot, lds);
+            gs_accept<DT>(st, d, drop, tot[0], tot[1]);
+        } else {
+            double tot[1];
+            final_sums<1>(a.part, nb, tot, lds);
+            gs_accept<DT>(st, d, drop, tot[0], 0.0);
         }
     }
 }

@@ -89,6 +89,7 @@ def _load():
         "guess_extrap_weights": (I, [I, I, C.POINTER(D)]),
         "guess_spextrap_weights": (I, [I, I, C.POINTER(D)]),
         "guess_history_get": (I, [P, I, I, P]),
+        "guess_history_raw": (I, [P, I, I, P, C.POINTER(D)]),
         "guess_proj_factor": (I, [P, C.POINTER(D), C.POINTER(I)]),
         "workload_plane_wave_rhs": (I, [I, I, C.POINTER(I), C.POINTER(D), C.POINTER(D), P, P]),
         "workload_gaussian_rhs": (I, [I, C.POINTER(D), D, D, P, P]),
@@ -113,7 +114,7 @@ EXPORTED = (
     "pcg_solve", "pcg_solve_ex", "guess_create", "guess_create_ex", "guess_destroy",
     "guess_set_stream", "guess_set_op", "guess_workspace_bytes", "guess_form", "guess_update",
     "guess_get_info", "guess_reset", "guess_extrap_weights", "guess_spextrap_weights", "guess_history_get",
-    "guess_proj_factor", "guess_next_slot",
+    "guess_history_raw", "guess_proj_factor", "guess_next_slot",
     "workload_plane_wave_rhs", "workload_gaussian_rhs", "vec_multidot", "vec_combine", "guess_strerror",
     "guess_last_error", "guess_copy_kernel", "guess_profile", "guess_kernel_times",
 )
@@ -288,6 +289,14 @@ def guess_spextrap_weights(m, k):
 
 def guess_history_get(g, which, j, out) -> None:
     _check(_lib.guess_history_get(g, which, j, addr(out, _sizes.get(g), "out")))
+
+
+def guess_history_raw(g, which, j, out) -> float:
+    """Stored values of history vector j, widened without scale, into out; returns the FP64
+    scale that turns them into the true values."""
+    sc = C.c_double(0.0)
+    _check(_lib.guess_history_raw(g, which, j, addr(out, _sizes.get(g), "out"), C.byref(sc)))
+    return sc.value
 
 
 def guess_proj_factor(g):

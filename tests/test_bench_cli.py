@@ -32,6 +32,13 @@ def test_byte_model_closed_forms():
     assert sum(bench.kernel_bytes("projqr", "update", N, s, M, M, False)) == N * (7 * M * s + 40)
     # variable coefficient: the fused apply also reads the face arrays
     assert bench.kernel_bytes("proj", "update", N, s, 5, M, False, faces=123)[0] == N * (16 + 5 * s) + 123
+    # FP16: the Gram-Schmidt pass also forms x - X c1 (for the pair's exponent), a restart
+    # writes A x before the pair is stored, and a ring store may store its slot twice
+    assert sum(bench.kernel_bytes("proj_l2", "update", N, 2, 5, M, False, dtype="f16")) == N * (5 * 5 * 2 + 4 + 48)
+    assert sum(bench.kernel_bytes("proj", "update", N, 2, 0, M, True, dtype="f16")) == N * (32 + 4)
+    assert bench.kernel_bytes("extrap", "update", N, 2, 8, M, False, dtype="f16") == [N * 10, 0]
+    assert bench.kernel_bytes("extrap", "update", N, 2, 8, M, False, dtype="f16", fixed=True) == [N * 10, N * 10]
+    assert bench.kernel_names("extrap", "update", "f16") == ["ring_store", "ring_fix"]
 
 
 def test_mode_flags_parse(monkeypatch):

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("method", ["extrap", "spextrap", "last", "proj", "projqr", "proj_l2", "projqr_l2"])
-@pytest.mark.parametrize("dtype", ["f64", "bf16"])
+@pytest.mark.parametrize("dtype", ["f64", "bf16", "f16"])
 def test_bench_bytes_match_library(lib, method, dtype):
     import torch
 
@@ -39,7 +39,7 @@ def test_bench_bytes_match_library(lib, method, dtype):
                 kf = min(deg, kd - 1) + 1 if kd > 0 else 0
             else:
                 kf = kd if method.startswith("proj") else min(kd, Mm)
-            want = sum(bench.kernel_bytes(method, "form", N, s, kf, Mm, False))
+            want = sum(bench.kernel_bytes(method, "form", N, s, kf, Mm, False, dtype=dtype))
             if method in ("extrap", "spextrap", "last") and kd == 0:
                 want = 8 * N                 # zero guess
             assert want == info["form_bytes"], (q, "form")
@@ -47,7 +47,12 @@ def test_bench_bytes_match_library(lib, method, dtype):
             info = L.guess_get_info(g)
             d = kd
             restart = (d == 0 or Mm == 1) if method.startswith("projqr") else (d == 0 or d >= Mm)
-            want = sum(bench.kernel_bytes(method, "update", N, s, d, Mm, restart and method.startswith("proj")))
+            ring = method in bench.RING
+            fixed = dtype == "f16" and ring and info["update_bytes"] > 1.5 * N * (8 + s)
+            if dtype == "f16" and ring:
+                assert info["update_bytes"] in (N * (8 + s), 2 * N * (8 + s))
+            want = sum(bench.kernel_bytes(method, "update", N, s, d, Mm, restart and method.startswith("proj"),
+                                          dtype=dtype, fixed=fixed))
             assert want == info["update_bytes"], (q, "update", d)
     finally:
         L.guess_destroy(g)

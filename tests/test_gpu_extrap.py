@@ -90,20 +90,27 @@ def test_sparse_lowprec_within_fp32_bound(lib, dtype):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f16", "bf16"])
 def test_ring_store_bit_exact(lib, dtype):
-    """Stored values equal the oracle's two-step round-to-nearest-even."""
+    """Stored values equal the oracle's two-step round-to-nearest-even (FP16: of 2^e x, e from
+    max |x|; here one element of 20000 fixes e = 0 so the crafted ties stay ties)."""
     import torch
 
     announce(f"ring store {dtype}")
     L = lib
     # ties, subnormals, overflow, signed zero, and double-rounding cases
     # (FP64 -> FP32 lands exactly on an FP16 / BF16 midpoint)
-    special = np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -11, 1 + 3 * 2 ** -11, 1 + 2 ** -24,
-                        1 + 3 * 2 ** -24, 65504.0, 65519.0, 2.0 ** -24, 3e-8, -0.0, 0.0, 1e-40,
-                        -2.5, 3.0e38, 1e300 if dtype == "f64" else 1.0,
-                        1 + 2 ** -11 + 2 ** -30, -(1 + 2 ** -11 + 2 ** -30), 1 + 2 ** -8 + 2 ** -30,
-                        3 * (1 + 2 ** -11) + 2 ** -28])
+    special = [1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -11, 1 + 3 * 2 ** -11, 1 + 2 ** -24,
+               1 + 3 * 2 ** -24, 2.0 ** -24, 3e-8, -0.0, 0.0, 1e-40, -2.5,
+               1 + 2 ** -11 + 2 ** -30, -(1 + 2 ** -11 + 2 ** -30), 1 + 2 ** -8 + 2 ** -30,
+               3 * (1 + 2 ** -11) + 2 ** -28]
+    if dtype == "f16":
+        special = [20000.0] + special + [2 ** 14 + 2 ** 3 + 2 ** -20]
+    else:
+        special += [65504.0, 65519.0, 3.0e38, 1e300 if dtype == "f64" else 1.0]
+    special = np.array(special)
     for N in (1, 3, 5, 1030, 70001):
         v = synth.random_vectors(N, 1, N)[0] * 10.0 ** np.random.default_rng(N).integers(-6, 4, N)
+        if dtype == "f16":
+            v = np.clip(v, -19000.0, 19000.0)
         v[: min(N, len(special))] = special[: min(N, len(special))]
         g = L.guess_create_ex(N, 2, L.EXTRAP, 0, L.DTYPES[dtype])
         try:
@@ -111,10 +118,73 @@ def test_ring_store_bit_exact(lib, dtype):
             out = torch.empty(N, dtype=torch.float64, device="cuda")
             L.guess_history_get(g, 0, 0, out)
             got = host(out)
+            raw = torch.empty(N, dtype=torch.float64, device="cuda")
+            scale = L.guess_history_raw(g, 0, 0, raw)
+            got_raw = host(raw)
         finally:
             L.guess_destroy(g)
-        want = lowprec.round_store(v, dtype)
+        e = lowprec.f16_scale_exp(float(np.max(np.abs(v)))) if dtype == "f16" else 0
+        want = lowprec.round_store(v, dtype, e)
         assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), (dtype, N)
+        assert np.array_equal(got_raw.view(np.uint64), lowprec.decode(lowprec.stored_bits(v, dtype, e), dtype).view(
+            np.uint64)), (dtype, N)
+        assert scale == 2.0 ** -e, (dtype, N, scale, e)
+
+
+@pytest.mark.parametrize("mags", [(1e6, 1e6), (1e-6, 1e-6), (1e-6, 1e6), (1.0, 3e4)])
+@pytest.mark.parametrize("N", [1027, 70001])
+def test_f16_ring_scaled_slots(lib, mags, N):
+    """FP16 slots hold round(2^e x), e from max |x| (max |x| 2^e in [2^14, 2^15)), so solutions
+    far outside FP16's range (|x| ~ 1e6, 1e-6) are stored with FP16's relative precision: the
+    raw stored bits and each slot's scale 2^-e equal the oracle's, and the guesses (weights
+    beta_j 2^-e_j, FP32 accumulation) meet the FP32 summation bound around the oracle's exact
+    evaluation of the stored values.  Magnitudes sweep geometrically from the first to the
+    second value, so the exponent of the next solution differs from the previous one's (the
+    slot is stored again) or not (one pass), and the update's byte count says which."""
+    import torch
+
+    announce(f"extrap f16 scaled slots mags={mags} N={N}")
+    L = lib
+    M, m, T = 8, 2, 12
+    g = L.guess_create_ex(N, M, L.EXTRAP, m, L.F16)
+    ref = extrap.ExtrapHistory(M, m, "f16")
+    rng = np.random.default_rng([N, int(np.log10(mags[0]) + 10), int(np.log10(mags[1]) + 10)])
+    base = rng.standard_normal(N)
+    x0 = torch.empty(N, dtype=torch.float64, device="cuda")
+    raw = torch.empty(N, dtype=torch.float64, device="cuda")
+    u = 2.0 ** -24
+    fixes = 0
+    try:
+        for s in range(T):
+            mag = mags[0] * (mags[1] / mags[0]) ** (s / (T - 1))
+            x = mag * (base + 0.1 * s * rng.standard_normal(N))
+            if s > 0:
+                L.guess_form(g, None, x0)
+                got, want = host(x0), ref.form(N=N)
+                k = len(ref.hist)
+                beta = extrap.to_f64(extrap.beta_ls_exact(min(m, k - 1), k))
+                magsum = sum(abs(b) * np.abs(h) for b, h in zip(beta, ref.hist))
+                assert_within(got, want, (k + 1) * u * magsum + u * np.abs(want) + 1e-300, ref.hist,
+                              f"f16 scaled step {s}")
+            prev_e = ref.exps[-1] if ref.exps else 0
+            L.guess_update(g, dev(x))
+            ref.update(x)
+            e = ref.exps[-1]
+            info = L.guess_get_info(g)
+            fixed = e != prev_e
+            fixes += fixed
+            assert info["update_bytes"] == N * 10.0 * (2 if fixed else 1), (s, e, prev_e)
+            scale = L.guess_history_raw(g, 0, info["count"] - 1, raw)
+            assert scale == 2.0 ** -e, (s, scale, e)
+            want_raw = lowprec.decode(lowprec.stored_bits(x, "f16", e), "f16")
+            assert np.array_equal(host(raw).view(np.uint64), want_raw.view(np.uint64)), s
+            assert np.all(np.isfinite(want_raw)) and np.max(np.abs(want_raw)) <= 2 ** 15
+    finally:
+        L.guess_destroy(g)
+    if mags[0] == mags[1]:
+        assert fixes < T // 2      # the first store, and the steps whose max |x| crosses a power of two
+    else:
+        assert fixes >= 3
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
