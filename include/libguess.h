@@ -357,6 +357,21 @@ int workload_gaussian_rhs(int n, const double *center, double sigma, double amp,
  * deterministic two-stage reduction; out is a host array.  Synchronises. */
 int vec_multidot(int64_t N, int K, const double *V, const double *y, double *out,
                  void *stream);
+/*
+ * vec_multidot for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, kernels and results (bit for bit) as vec_multidot, but the
+ * reduction's scratch (the partial rows and the results) is a static device
+ * array of the library, 128.5 KiB per GPU, held until the process ends; no
+ * hipMalloc / hipFree / allocating routine is called.  K above 64 is
+ * rejected (GUESS_EINVAL): the scratch holds 64 results.  Every call on one
+ * GPU shares that GPU's array, so calls that overlap on one GPU (other
+ * streams or host threads) race; the library serialises only the one-time
+ * lookup of the array's device address.  out is a host array of K doubles.
+ * Synchronises.
+ */
+int vec_multidot_noalloc(int64_t N, int K, const double *V, const double *y, double *out,
+                         void *stream);
 /* y = sum_k c_k v_k (c host array of K doubles, V as above). */
 int vec_combine(int64_t N, int K, const double *V, const double *c, double *y,
                 void *stream);

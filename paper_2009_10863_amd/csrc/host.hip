@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <new>
 #include <string>
@@ -1074,6 +1075,58 @@ extern "C" int vec_multidot(int64_t N, int K, const double *V, const double *y, 
     LG_TRY(lg::launch_multidot(N, K, V, y, g_vec.part, g_vec.out, s));
     LG_TRY(check_launch("vec_multidot"));
     LG_HIP(hipMemcpyAsync(out, g_vec.out, sizeof(double) * K, hipMemcpyDeviceToHost, s));
+    LG_HIP(hipStreamSynchronize(s));
+    return GUESS_OK;
+}
+
+// ---------------------------------------------------------------------- allocation-free multi-dot
+// Scratch of vec_multidot_noalloc: the partial rows of the first reduction
+// stage (at most kMaxPartialBlocks rows of 8 values) followed by the K <= 64
+// results.  Every value the second stage reads was written by the first stage
+// of the same call, so nothing needs clearing.  Each GPU the library runs on
+// holds its own copy (128.5 KiB) until the process ends, and every call on
+// that GPU shares it.  In host code `scratch` only names the symbol: its
+// device address on the current GPU comes from hipGetSymbolAddress.
+constexpr int kNoallocPart = lg::kMaxPartialBlocks * 8;
+constexpr int kNoallocK = 64;
+static __device__ __align__(256) double scratch[kNoallocPart + kNoallocK];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the current GPU's scratch, looked up once per device with
+// that device current.
+static int scratch_address(double **out) {
+    int dev = -1;
+    LG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(GUESS_EINVAL, "vec_multidot_noalloc: device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        LG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(GUESS_EHIP, "vec_multidot_noalloc: no device address for the scratch array");
+        g_scratch_dev[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return GUESS_OK;
+}
+
+extern "C" int vec_multidot_noalloc(int64_t N, int K, const double *V, const double *y, double *out,
+                                    void *stream) {
+    if (N < 1 || !V || !y || !out) return fail(GUESS_EINVAL, "vec_multidot_noalloc: bad argument");
+    if (K < 1 || K > kNoallocK)
+        return fail(GUESS_EINVAL, "vec_multidot_noalloc: K must be in 1..64 (the static scratch holds 64 results)");
+    if (lg::reduce_blocks() * 8 > kNoallocPart)
+        return fail(GUESS_EINVAL, "vec_multidot_noalloc: more partial rows than the static scratch holds");
+    double *sp = nullptr;
+    LG_TRY(scratch_address(&sp));
+    hipStream_t s = (hipStream_t)stream;
+    LG_TRY(lg::launch_multidot(N, K, V, y, sp, sp + kNoallocPart, s));
+    LG_TRY(check_launch("vec_multidot_noalloc"));
+    LG_HIP(hipMemcpyAsync(out, sp + kNoallocPart, sizeof(double) * K, hipMemcpyDeviceToHost, s));
     LG_HIP(hipStreamSynchronize(s));
     return GUESS_OK;
 }

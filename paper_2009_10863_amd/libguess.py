@@ -94,6 +94,7 @@ def _load():
         "workload_plane_wave_rhs": (I, [I, I, C.POINTER(I), C.POINTER(D), C.POINTER(D), P, P]),
         "workload_gaussian_rhs": (I, [I, C.POINTER(D), D, D, P, P]),
         "vec_multidot": (I, [I64, I, P, P, C.POINTER(D), P]),
+        "vec_multidot_noalloc": (I, [I64, I, P, P, C.POINTER(D), P]),
         "vec_combine": (I, [I64, I, P, C.POINTER(D), P, P]),
         "guess_strerror": (C.c_char_p, [I]),
         "guess_last_error": (C.c_char_p, []),
@@ -115,7 +116,7 @@ EXPORTED = (
     "guess_set_stream", "guess_set_op", "guess_workspace_bytes", "guess_form", "guess_update",
     "guess_get_info", "guess_reset", "guess_extrap_weights", "guess_spextrap_weights", "guess_history_get",
     "guess_history_raw", "guess_proj_factor", "guess_next_slot",
-    "workload_plane_wave_rhs", "workload_gaussian_rhs", "vec_multidot", "vec_combine", "guess_strerror",
+    "workload_plane_wave_rhs", "workload_gaussian_rhs", "vec_multidot", "vec_multidot_noalloc", "vec_combine", "guess_strerror",
     "guess_last_error", "guess_copy_kernel", "guess_profile", "guess_kernel_times",
 )
 
@@ -342,6 +343,15 @@ def vec_multidot(N, K, V, y, stream=None):
     ok = N > 0 and K > 0
     _check(_lib.vec_multidot(N, K, addr(V, N * K if ok else None, "V"), addr(y, N if ok else None, "y"), out,
                              stream))
+    return list(out)
+
+
+def vec_multidot_noalloc(N, K, V, y, stream=None):
+    """vec_multidot without any device allocation (the library's static scratch)."""
+    out = (C.c_double * K)()
+    ok = N > 0 and K > 0
+    _check(_lib.vec_multidot_noalloc(N, K, addr(V, N * K if ok else None, "V"), addr(y, N if ok else None, "y"),
+                                     out, stream))
     return list(out)
 
 
