@@ -55,8 +55,8 @@ def kernel_names(method, call, dtype="f64"):
     return KERNELS[(method, call)]
 
 
-def kernel_bytes(method, call, N, s, k_or_d, M, restart, faces=0, dtype="f64", fixed=False):
-    """Algorithmic HBM bytes of each kernel of one call (list, launch order).
+def kernel_rw(method, call, N, s, k_or_d, M, restart, faces=0, dtype="f64", fixed=False):
+    """Algorithmic HBM bytes (read, written) of each kernel of one call (list, launch order).
 
     `faces`: bytes of the operator's face arrays, read by the fused operator
     apply of a variable-coefficient workload.  `fixed`: an FP16 ring store that
@@ -64,25 +64,39 @@ def kernel_bytes(method, call, N, s, k_or_d, M, restart, faces=0, dtype="f64", f
     f16 = dtype == "f16"
     if method in RING:
         if call == "form":
-            return [N * (k_or_d * s + 8)] if k_or_d > 0 else []
+            return [(N * k_or_d * s, N * 8)] if k_or_d > 0 else []
         if f16:
-            return [N * (8 + s), N * (8 + s) if fixed else 0]
-        return [N * (8 + s)]
+            return [(N * 8, N * s), (N * 8, N * s) if fixed else (0, 0)]
+        return [(N * 8, N * s)]
     d = k_or_d
     if call == "form":
-        return [N * (d * s + 8) if d > 0 else 0, 0, N * (d * s + 8)]
+        return [(N * (d * s + 8), 0) if d > 0 else (0, 0), (0, 0), (N * d * s, N * 8)]
     if restart and f16:
         # the apply pass reads x and writes A x with max |x|, |A x|; the write kernel stores the pair
-        return [N * 16 + faces, 0, 0, 0, N * (16 + 2 * s), 0]
+        return [(N * 8 + faces, N * 8), (0, 0), (0, 0), (0, 0), (N * 16, N * 2 * s), (0, 0)]
     if restart:
-        return [N * (8 + 2 * s) + faces, 0, 0, 0, 0, 0]
+        return [(N * 8 + faces, N * 2 * s), (0, 0), (0, 0), (0, 0), (0, 0), (0, 0)]
     if f16:
         reorth = N * (2 * d * s + 16)      # also forms x - X c1 for the pair's exponent
     else:
         reorth = N * ((1 if method.endswith("_l2") else 2) * d * s + 8)
+    apply = (N * (8 + d * s) + faces, N * 8)
     if method.startswith("projqr") and d == M:      # rolling drop: every column rotated in place
-        return [N * (16 + d * s) + faces, 0, reorth, 0, N * (4 * d * s + 16), 0]
-    return [N * (16 + d * s) + faces, 0, reorth, 0, N * (2 * d * s + 16 + 2 * s), 0]
+        return [apply, (0, 0), (reorth, 0), (0, 0), (N * (2 * d * s + 16), N * 2 * d * s), (0, 0)]
+    return [apply, (0, 0), (reorth, 0), (0, 0), (N * (2 * d * s + 16), N * 2 * s), (0, 0)]
+
+
+def kernel_bytes(method, call, N, s, k_or_d, M, restart, faces=0, dtype="f64", fixed=False):
+    """Algorithmic HBM bytes of each kernel of one call (list, launch order): read + written."""
+    return [r + w for r, w in kernel_rw(method, call, N, s, k_or_d, M, restart, faces, dtype, fixed)]
+
+
+def mixed_roof(read, write, read_roof, write_roof):
+    """Bandwidth a kernel moving `read` and `write` bytes reaches at the measured read and
+    write roofs: (read + write) / (read / R + write / W)."""
+    if read + write <= 0:
+        return None
+    return (read + write) / (read / read_roof + write / write_roof)
 
 
 def parse():
@@ -134,7 +148,7 @@ def parse():
     p.add_argument("--maxit", type=int, default=5000)
     p.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     p.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
-    p.add_argument("--cpu-steps", type=int, default=12)
+    p.add_argument("--cpu-steps", type=int, default=6)
     p.add_argument("--no-small-sequence", dest="small", action="store_false", default=True,
                    help="skip the 32^3 whole-sequence run (e.g. under a profiler)")
     p.add_argument("--precision-steps", type=int, default=10,
@@ -145,24 +159,33 @@ def parse():
     return p.parse_args()
 
 
-def copy_roof(L, nbytes=1 << 30, reps=5):
-    """Bandwidth of the library's plain copy kernel (nbytes read + nbytes written)."""
+def copy_roof(L, nbytes=1 << 30, reps=5, mode=None):
+    """Bandwidth of the library's plain copy kernel (nbytes read + nbytes written), or with
+    `mode` of its read-only (nbytes read) or write-only (nbytes written) reference."""
     import torch
 
+    mode = L.ROOF_COPY if mode is None else mode
     src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
+    dst = torch.empty(2048 if mode == L.ROOF_READ else nbytes // 8, dtype=torch.float64, device="cuda")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    L.guess_copy_kernel(dst, src, nbytes, L.stream_handle())
+    L.guess_roof_kernel(mode, dst, src, nbytes, L.stream_handle())
     ts = []
     for _ in range(reps):
         ev[0].record()
-        L.guess_copy_kernel(dst, src, nbytes, L.stream_handle())
+        L.guess_roof_kernel(mode, dst, src, nbytes, L.stream_handle())
         ev[1].record()
         torch.cuda.synchronize()
         ts.append(ev[0].elapsed_time(ev[1]))
     del src, dst
     t = sorted(ts)[len(ts) // 2]
-    return 2 * nbytes / (t * 1e-3) / 1e9
+    return (2 if mode == L.ROOF_COPY else 1) * nbytes / (t * 1e-3) / 1e9
+
+
+def roofs(L, reps=9):
+    """Measured copy, read-only and write-only bandwidths (GB/s), 1 GiB each, median of `reps`
+    launches (single measurements vary by about 3 % between runs)."""
+    return {"copy_roof_GBps": copy_roof(L, reps=reps), "read_roof_GBps": copy_roof(L, reps=reps, mode=L.ROOF_READ),
+            "write_roof_GBps": copy_roof(L, reps=reps, mode=L.ROOF_WRITE)}
 
 
 def hbm_traffic(kernel):
@@ -200,21 +223,30 @@ def hbm_traffic(kernel):
 
 
 def cpu_baseline(args, s_bytes):
-    """The oracle (NumPy FP64) timed on the host: guess form+update on a bounded sample.
+    """The oracle (NumPy FP64) timed on the host: guess form+update on a bounded sample of the
+    benchmark's own workload.
 
-    Sample: `cpu_steps` steady-state steps of EXTRAP(m, M) and PROJ(M) at the
-    benchmark grid, full histories of random vectors; the oracle's own
-    operator is applied once per projection update.  Reported in the same
-    algorithmic GB/s as the GPU value.
+    Sample: the plane-wave sequence of the benchmark (same seed, modes, dt, grid, M, degree),
+    solutions exact (each one the same combination of the modes' DST-I solutions as its
+    right-hand side is of the modes), histories filled over M untimed steps; then
+    `cpu_steps` steps of EXTRAP(m, M) and PROJ(M) form+update are timed on one host thread
+    and, from the same state, on all host cores (BLAS threads; NumPy's elementwise passes
+    stay on one).  The oracle's own operator is applied once per projection update.
+    Reported in the same algorithmic GB/s as the GPU value.
     """
     import numpy as np
     from threadpoolctl import threadpool_limits
 
-    with threadpool_limits(limits=1):   # one host thread throughout, BLAS included
-        return _cpu_baseline(args, np)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    return _cpu_baseline(args, np, cores, threadpool_limits)
 
 
-def _cpu_baseline(args, np):
+def _cpu_baseline(args, np, cores, threadpool_limits):
+    import copy
+
     import synth
     from oracle import operator as oop
     from oracle.extrap import ExtrapHistory
@@ -223,52 +255,66 @@ def _cpu_baseline(args, np):
 
     n, M, m = args.n, args.M, args.degree
     N = n ** 3
-    rng = np.random.default_rng(1)
     Aop = oop.Operator(n)
+    t_setup = time.perf_counter()
+    p = synth.plane_wave_params(args.seed, args.modes)
+    F = synth.plane_wave_modes(p, n)
+    U = np.stack([oop.dst_solve(f, n, workers=cores) for f in F])      # A u_k = f_k
+    amps = lambda step: synth.mode_amplitudes(p, step * args.dt)     # noqa: E731
     e = ExtrapHistory(M, m)
-    for _ in range(M):
-        e.update(rng.standard_normal(N))
     P = AOrthoProjection(M, Aop, 1e-6)
-    for _ in range(M - 2):
-        P.update(rng.standard_normal(N))
-    b = rng.standard_normal(N)
-    nbytes, secs = 0.0, 0.0
-    for _ in range(args.cpu_steps):
-        x = rng.standard_normal(N)
-        t0 = time.perf_counter()
-        e.form(b)
-        e.update(x)
-        secs += time.perf_counter() - t0
-        nbytes += N * (M * 8 + 8) + N * 16
-        d = P.d
-        t0 = time.perf_counter()
-        P.form(b)
-        P.update(x)
-        secs += time.perf_counter() - t0
-        restart = d == 0 or d >= M
-        nbytes += 2 * N * (d * 8 + 8) + (N * (8 + 16) if restart else N * (5 * d * 8 + 16 + 40))
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except Exception:
-        cores = os.cpu_count()
+    with threadpool_limits(limits=cores):
+        for step in range(1, M + 1):
+            x = amps(step) @ U
+            e.update(x)
+            P.update(x)
+    setup_s = time.perf_counter() - t_setup
+    state = copy.deepcopy((e, P))
+
+    def timed(threads):
+        ee, PP = copy.deepcopy(state)
+        nbytes, secs = 0.0, 0.0
+        with threadpool_limits(limits=threads):
+            for step in range(M + 1, M + 1 + args.cpu_steps):
+                a = amps(step)
+                b, x = a @ F, a @ U
+                t0 = time.perf_counter()
+                ee.form(N=N)
+                ee.update(x)
+                secs += time.perf_counter() - t0
+                nbytes += N * (M * 8 + 8) + N * 16
+                d = PP.d
+                t0 = time.perf_counter()
+                PP.form(b)
+                PP.update(x)
+                secs += time.perf_counter() - t0
+                restart = d == 0 or d >= M
+                nbytes += 2 * N * (d * 8 + 8) + (N * (8 + 16) if restart else N * (5 * d * 8 + 16 + 40))
+        return nbytes / secs / 1e9, secs, PP.d
+
+    one, one_s, d_end = timed(1)
+    allc, all_s, _ = timed(cores)
     # the whole small sequence (32^3, 4 plane waves, 50 steps, dt = 0.01): guess -> PCG -> update
     n1 = 32
     op1 = oop.Operator(n1)
     p1 = synth.plane_wave_params(0, 4)
     rhs1 = [synth.plane_wave_rhs(p1, n1, 0.01 * (k + 1)) for k in range(50)]
     seq = {}
-    for meth in ("zero", "last", "extrap", "proj"):
-        t0 = time.perf_counter()
-        r = run_sequence(op1, rhs1, meth, M, m, rtol=args.rtol)
-        seq[meth] = {"wall_s": round(time.perf_counter() - t0, 3), "pcg_iters": int(sum(r["iters"]))}
+    with threadpool_limits(limits=1):
+        for meth in ("zero", "last", "extrap", "proj"):
+            t0 = time.perf_counter()
+            r = run_sequence(op1, rhs1, meth, M, m, rtol=args.rtol)
+            seq[meth] = {"wall_s": round(time.perf_counter() - t0, 3), "pcg_iters": int(sum(r["iters"]))}
     return {
-        "value": nbytes / secs / 1e9,
+        "value": allc,
         "unit": "GB/s",
-        "cores": 1,
-        "cores_available": cores,
+        "cores": cores,
         "kind": "oracle",
-        "sample": f"{args.cpu_steps} steady-state steps of EXTRAP({m},{M}) + PROJ({M}) form+update "
-                  f"at {n}^3, FP64 NumPy on one thread, {secs:.1f} s",
+        "sample": f"{args.cpu_steps} steps (after {M} that fill the histories) of EXTRAP({m},{M}) + PROJ({M}) "
+                  f"form+update on the benchmark's {args.modes}-mode plane-wave sequence at {n}^3, exact "
+                  f"solutions; FP64 NumPy with {cores} BLAS threads, {all_s:.1f} s timed "
+                  f"(setup {setup_s:.0f} s); projection history at d = {d_end} at the end",
+        "one_thread": {"value": one, "unit": "GB/s", "cores": 1, "timed_s": round(one_s, 2)},
         "small_sequence": {"workload": f"{n1}^3, 4 plane-wave modes, 50 steps, dt = 0.01, M = {M}, "
                                        f"EXTRAP({m},{M}) / PROJ({M}), guess -> PCG -> update, one thread",
                            "methods": seq},
@@ -364,7 +410,7 @@ def isolated(args, L):
     print(json.dumps({"isolated_GBps": {k: round(v, 1) for k, v in out.items()},
                       "isolated_us": {k: round(v, 2) for k, v in us.items()},
                       "grid": [n, n, nz], "M": M, "reps": reps,
-                      "copy_roof_GBps": copy_roof(L), "peak_GBps": HBM_PEAK_GBS}), flush=True)
+                      **roofs(L), "peak_GBps": HBM_PEAK_GBS}), flush=True)
 
 
 def small_sequence(args):
@@ -570,7 +616,8 @@ def main():
     if args.concurrent:
         concurrent_run(args, L)
         return
-    roof = copy_roof(L)
+    rf = roofs(L)
+    roof = rf["copy_roof_GBps"]
     n, N, M = args.n, args.n ** 3, args.M
     methods = [m.strip() for m in args.methods.split(",") if m.strip()]
     kappa = None
@@ -676,19 +723,22 @@ def main():
                 restart = m.startswith("proj") and (dd == 0 or dd >= M)
             for call, times, kdd in (("form", tf, kd_form), ("update", tu, inf1["count"])):
                 names = kernel_names(m, call, dtype)
-                byts = kernel_bytes(m, call, N, s, kdd, M, restart, faces, dtype, fixed)
-                for name, ms, by in zip(names, times, byts):
+                rws = kernel_rw(m, call, N, s, kdd, M, restart, faces, dtype, fixed)
+                for name, ms, (rb, wb) in zip(names, times, rws):
                     # every kernel of the call counts in the guess time; the
                     # per-kernel table keeps the streaming kernels that moved data
+                    by = rb + wb
                     S["guess_ms"] += ms
                     S["guess_bytes"] += by
                     if by == 0:
                         continue
                     key = name if m in ("extrap", "proj") else f"{name}:{m}"
-                    ks = kstat.setdefault(key, [0, 0.0, 0.0])
+                    ks = kstat.setdefault(key, [0, 0.0, 0.0, 0.0, 0.0])
                     ks[0] += 1
                     ks[1] += ms
                     ks[2] += by
+                    ks[3] += rb
+                    ks[4] += wb
 
         try:
             for step in range(1, warmup + 1):
@@ -718,7 +768,7 @@ def main():
     tot_ms = sum(S["guess_ms"] for S in stats.values())
     value = tot_bytes / (tot_ms * 1e-3) / 1e9
     dom = max(kstat.items(), key=lambda kv: kv[1][1])
-    dname, (dl, dms, dby) = dom
+    dname, (dl, dms, dby, drb, dwb) = dom
     achieved = (dby / dl) / (dms / dl * 1e-3) / 1e9
     per_method = {}
     for m, S in stats.items():
@@ -732,8 +782,13 @@ def main():
         }
         if len(fields) > 1:
             per_method[m]["pcg_iters_per_step_by_field"] = {f: float(np.mean(v)) for f, v in S["field_iters"].items()}
-    kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / v[0], "GBps": v[2] / (v[1] * 1e-3) / 1e9,
-                   "bytes_per_launch": v[2] / v[0]} for k, v in sorted(kstat.items())}
+    R, W = rf["read_roof_GBps"], rf["write_roof_GBps"]
+    kernels = {}
+    for k, v in sorted(kstat.items()):
+        gbps = v[2] / (v[1] * 1e-3) / 1e9
+        mr = mixed_roof(v[3], v[4], R, W)
+        kernels[k] = {"launches": v[0], "avg_us": 1e3 * v[1] / v[0], "GBps": gbps, "bytes_per_launch": v[2] / v[0],
+                      "read_fraction": v[3] / v[2], "mixed_roof_GBps": mr, "frac_of_mixed_roof": gbps / mr}
     # counter bytes of the profiled launches, scaled to this run's launches of the same kernel
     # (their mix of history sizes d differs with the number of steps)
     tr = hbm_traffic(dname)
@@ -765,7 +820,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "traffic_ratio": traffic_ratio,
                      "bytes_per_launch": dby / dl, "avg_us": 1e3 * dms / dl,
-                     "copy_roof_GBps": roof, "frac_of_copy_roof": achieved / roof},
+                     "copy_roof_GBps": roof, "frac_of_copy_roof": achieved / roof,
+                     "read_roof_GBps": R, "write_roof_GBps": W,
+                     "mixed_roof_GBps": mixed_roof(drb, dwb, R, W),
+                     "frac_of_mixed_roof": achieved / mixed_roof(drb, dwb, R, W)},
+        "guess_mixed_roof_GBps": mixed_roof(sum(v[3] for v in kstat.values()), sum(v[4] for v in kstat.values()), R, W),
         "methods": per_method,
         "kernels": kernels,
     }

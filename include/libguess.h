@@ -384,6 +384,19 @@ const char *guess_last_error(void);
  * (bandwidth reference for the roofline). */
 int guess_copy_kernel(void *dst, const void *src, size_t bytes, void *stream);
 
+/* Bandwidth references of the roofline (§6.2 of the paper judges each
+ * kernel against a measured copy; a read roof and a write roof say how much
+ * of a kernel's reads and writes HBM can carry): the same 16-byte
+ * non-temporal accesses as the guess kernels.
+ *   GUESS_ROOF_COPY:  guess_copy_kernel (bytes read and bytes written);
+ *   GUESS_ROOF_READ:  reads `bytes` of src (multiple of 16 counted) and
+ *                     writes one FP64 partial sum per workgroup into dst,
+ *                     which must hold 2048 doubles (16 KiB);
+ *   GUESS_ROOF_WRITE: writes `bytes` of dst (src unused, may be NULL).
+ * Device pointers, 16-byte aligned; EINVAL otherwise or for another mode. */
+enum { GUESS_ROOF_COPY = 0, GUESS_ROOF_READ = 1, GUESS_ROOF_WRITE = 2 };
+int guess_roof_kernel(int mode, void *dst, const void *src, size_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

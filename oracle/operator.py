@@ -158,11 +158,13 @@ def eigenvalues_const(n: int, shift: float = 10.0, c: float = None) -> np.ndarra
     return shift + s2[:, None, None] + s2[None, :, None] + s2[None, None, :]
 
 
-def dst_solve(b: np.ndarray, n: int, shift: float = 10.0, c: float = None) -> np.ndarray:
-    """Exact solution of A x = b (constant coefficient) by DST-I diagonalisation."""
+def dst_solve(b: np.ndarray, n: int, shift: float = 10.0, c: float = None, workers: int = None) -> np.ndarray:
+    """Exact solution of A x = b (constant coefficient) by DST-I diagonalisation.
+
+    `workers` lets scipy spread the independent 1-D transforms over threads."""
     from scipy.fft import dstn, idstn
 
     B = np.asarray(b, dtype=np.float64).reshape(n, n, n)
-    bh = dstn(B, type=1, norm="ortho")
+    bh = dstn(B, type=1, norm="ortho", workers=workers)
     xh = bh / eigenvalues_const(n, shift, c)
-    return idstn(xh, type=1, norm="ortho").reshape(-1)
+    return idstn(xh, type=1, norm="ortho", workers=workers).reshape(-1)

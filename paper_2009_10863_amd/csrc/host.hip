@@ -1144,6 +1144,24 @@ extern "C" int guess_copy_kernel(void *dst, const void *src, size_t bytes, void 
     return check_launch("guess_copy_kernel");
 }
 
+extern "C" int guess_roof_kernel(int mode, void *dst, const void *src, size_t bytes, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    switch (mode) {
+        case GUESS_ROOF_COPY: return guess_copy_kernel(dst, src, bytes, stream);
+        case GUESS_ROOF_READ:
+            if (!dst || !src) return fail(GUESS_EINVAL, "guess_roof_kernel: NULL argument");
+            if (!aligned16(src) || !aligned16(dst)) return fail(GUESS_EINVAL, "guess_roof_kernel: need 16-byte alignment");
+            LG_TRY(lg::launch_read(src, bytes, (double *)dst, s));
+            return check_launch("guess_roof_kernel");
+        case GUESS_ROOF_WRITE:
+            if (!dst) return fail(GUESS_EINVAL, "guess_roof_kernel: NULL argument");
+            if (!aligned16(dst)) return fail(GUESS_EINVAL, "guess_roof_kernel: need 16-byte alignment");
+            LG_TRY(lg::launch_write(dst, bytes, s));
+            return check_launch("guess_roof_kernel");
+    }
+    return fail(GUESS_EINVAL, "guess_roof_kernel: unknown mode");
+}
+
 // ====================================================================== errors
 extern "C" const char *guess_strerror(int code) {
     switch (code) {

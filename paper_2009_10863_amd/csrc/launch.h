@@ -125,6 +125,8 @@ int launch_multidot(int64_t N, int K, const double *V, const double *y, double *
                     double *out_dev, hipStream_t s);
 int launch_combine(int64_t N, int K, const double *V, const double *c, double *y, hipStream_t s);
 int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+int launch_read(const void *src, size_t bytes, double *out, hipStream_t s);
+int launch_write(void *dst, size_t bytes, hipStream_t s);
 int launch_plane_wave_rhs(int n, int K, const double *tabx, const double *taby,
                           const double *tabz, const double *amp, double *b, hipStream_t s);
 int launch_gaussian_rhs(int n, const double *center, double sigma, double amp, double *tab, double *b,

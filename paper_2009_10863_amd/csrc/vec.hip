@@ -1,5 +1,7 @@
 // Generic FP64 vector kernels (multi-dot, combination, copy) and the
 // plane-wave right-hand-side generator of the synthetic workloads.
+#include <cstdlib>
+
 #include "common.h"
 #include "launch.h"
 
@@ -90,6 +92,96 @@ int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
     const int64_t tail = (int64_t)(bytes - (size_t)n16 * 16);
     if (tail > 0)
         copy_tail_kernel<<<1, 64, 0, s>>>((const unsigned char *)src, (unsigned char *)dst, n16 * 16, tail);
+    return GUESS_OK;
+}
+
+// Read-only and write-only references with the same 16-byte non-temporal
+// accesses as the copy.  Each thread keeps U accesses in flight per step
+// (elements t, t + S, ..., t + (U-1) S of a grid-stride loop of stride U S,
+// S = threads in the grid), which a kernel streaming several vectors gets
+// from its several streams.  The read kernel sums what it streams (one
+// partial per workgroup into out, so no load can be dropped); the write
+// kernel fills with a constant.  Grid and U: see launch_read / launch_write.
+template <int U>
+__global__ __launch_bounds__(kBlock) void read_kernel(const d2 *__restrict__ src, int64_t n16,
+                                                      double *__restrict__ out) {
+    __shared__ double lds[kLdsDoubles];
+    const int64_t S = (int64_t)gridDim.x * kBlock;
+    double acc[1] = {0.0};
+    double part[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) part[u] = 0.0;
+    int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; t + (U - 1) * S < n16; t += U * S) {
+        d2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = __builtin_nontemporal_load(src + t + u * S);
+#pragma unroll
+        for (int u = 0; u < U; ++u) part[u] += v[u].x + v[u].y;
+    }
+    for (; t < n16; t += S) {
+        const d2 v = __builtin_nontemporal_load(src + t);
+        part[0] += v.x + v.y;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[0] += part[u];
+    block_partials<1>(acc, out, lds);
+}
+
+template <int U>
+__global__ __launch_bounds__(kBlock) void write_kernel(d2 *__restrict__ dst, int64_t n16, double v) {
+    const int64_t S = (int64_t)gridDim.x * kBlock;
+    const d2 w{v, v};
+    int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; t + (U - 1) * S < n16; t += U * S) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) __builtin_nontemporal_store(w, dst + t + u * S);
+    }
+    for (; t < n16; t += S) __builtin_nontemporal_store(w, dst + t);
+}
+
+// Launch shapes: the read kernel runs kMaxPartialBlocks workgroups with one
+// access in flight per thread and step, the write kernel one workgroup per
+// 256 accesses (no loop).  Measured on MI355X over 512 .. 2^20 workgroups and
+// 1 .. 8 accesses per step (1 GiB): reads peaked at 6.87 TB/s with about
+// 2048 x 256 accesses in flight (twice as many fell to 5.5 TB/s), writes at
+// 6.5-6.6 TB/s with the full grid (4.2-5.6 TB/s with 512-65536 workgroups
+// looping).  LIBGUESS_ROOF_GRID (workgroups; the read kernel's partial rows
+// cap it at kMaxPartialBlocks) and LIBGUESS_ROOF_UNROLL (1, 2, 4 or 8)
+// override the shape, for measurements.
+static int roof_env(const char *name, int dflt) {
+    const char *v = std::getenv(name);
+    return (v && *v) ? std::atoi(v) : dflt;
+}
+
+int launch_read(const void *src, size_t bytes, double *out, hipStream_t s) {
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 <= 0) return GUESS_OK;
+    int grid = roof_env("LIBGUESS_ROOF_GRID", kMaxPartialBlocks);
+    grid = grid < 1 ? 1 : (grid > kMaxPartialBlocks ? kMaxPartialBlocks : grid);
+    grid = stream_grid(n16, grid);
+    const d2 *p = (const d2 *)src;
+    switch (roof_env("LIBGUESS_ROOF_UNROLL", 1)) {
+        case 2: read_kernel<2><<<grid, kBlock, 0, s>>>(p, n16, out); break;
+        case 4: read_kernel<4><<<grid, kBlock, 0, s>>>(p, n16, out); break;
+        case 8: read_kernel<8><<<grid, kBlock, 0, s>>>(p, n16, out); break;
+        default: read_kernel<1><<<grid, kBlock, 0, s>>>(p, n16, out); break;
+    }
+    return GUESS_OK;
+}
+
+int launch_write(void *dst, size_t bytes, hipStream_t s) {
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 <= 0) return GUESS_OK;
+    int grid = roof_env("LIBGUESS_ROOF_GRID", grid_cap());
+    grid = stream_grid(n16, grid < 1 ? 1 : grid);
+    d2 *p = (d2 *)dst;
+    switch (roof_env("LIBGUESS_ROOF_UNROLL", 1)) {
+        case 2: write_kernel<2><<<grid, kBlock, 0, s>>>(p, n16, 1.0); break;
+        case 4: write_kernel<4><<<grid, kBlock, 0, s>>>(p, n16, 1.0); break;
+        case 8: write_kernel<8><<<grid, kBlock, 0, s>>>(p, n16, 1.0); break;
+        default: write_kernel<1><<<grid, kBlock, 0, s>>>(p, n16, 1.0); break;
+    }
     return GUESS_OK;
 }
 

@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("LIBGUESS_SO") or os.path.join(_HERE, "_lib", "libgues
 ZERO, LAST, EXTRAP, PROJ, SPEXTRAP, PROJ_QR = 0, 1, 2, 3, 4, 5
 INNER_A, INNER_L2 = 0, 1
 F64, F32, F16, BF16 = 0, 1, 2, 3
+ROOF_COPY, ROOF_READ, ROOF_WRITE = 0, 1, 2
 OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 STOP_RHS, STOP_INITRESID = 0, 1
 MAX_M = 16
@@ -99,6 +100,7 @@ def _load():
         "guess_strerror": (C.c_char_p, [I]),
         "guess_last_error": (C.c_char_p, []),
         "guess_copy_kernel": (I, [P, P, S, P]),
+        "guess_roof_kernel": (I, [I, P, P, S, P]),
         "guess_profile": (I, [P, I]),
         "guess_kernel_times": (I, [P, C.POINTER(D), I, C.POINTER(I)]),
     }
@@ -117,7 +119,7 @@ EXPORTED = (
     "guess_get_info", "guess_reset", "guess_extrap_weights", "guess_spextrap_weights", "guess_history_get",
     "guess_history_raw", "guess_proj_factor", "guess_next_slot",
     "workload_plane_wave_rhs", "workload_gaussian_rhs", "vec_multidot", "vec_multidot_noalloc", "vec_combine", "guess_strerror",
-    "guess_last_error", "guess_copy_kernel", "guess_profile", "guess_kernel_times",
+    "guess_last_error", "guess_copy_kernel", "guess_roof_kernel", "guess_profile", "guess_kernel_times",
 )
 
 
@@ -364,6 +366,15 @@ def vec_combine(N, K, V, c, y, stream=None) -> None:
 
 def guess_copy_kernel(dst, src, nbytes, stream=None) -> None:
     _check(_lib.guess_copy_kernel(addr(dst, nbytes, "dst", f64=False), addr(src, nbytes, "src", f64=False),
+                                  nbytes, stream))
+
+
+def guess_roof_kernel(mode, dst, src, nbytes, stream=None) -> None:
+    """Copy / read-only / write-only bandwidth reference (the read mode writes 2048 partial
+    sums into dst)."""
+    need_dst = 2048 * 8 if mode == ROOF_READ else nbytes
+    _check(_lib.guess_roof_kernel(mode, addr(dst, need_dst, "dst", f64=False),
+                                  addr(src, nbytes if mode != ROOF_WRITE else None, "src", f64=False),
                                   nbytes, stream))
 
 

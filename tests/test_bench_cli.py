@@ -55,3 +55,23 @@ def test_mode_flags_parse(monkeypatch):
     ):
         monkeypatch.setattr(sys, "argv", ["bench.py"] + argv)
         assert check(bench.parse()), argv
+
+
+def test_read_write_split_and_mixed_roof():
+    """Every kernel's bytes split into read and written parts that sum to the byte model, and
+    the mixed roof is the harmonic combination of the read and write roofs."""
+    N, M = 1000, 8
+    for method in ("extrap", "last", "spextrap", "proj", "projqr", "proj_l2", "projqr_l2"):
+        for dtype, s in (("f64", 8), ("f32", 4), ("f16", 2), ("bf16", 2)):
+            for call in ("form", "update"):
+                for d in range(0, M + 1):
+                    for restart in (False, True):
+                        rw = bench.kernel_rw(method, call, N, s, d, M, restart, 0, dtype, True)
+                        assert [r + w for r, w in rw] == bench.kernel_bytes(method, call, N, s, d, M, restart, 0,
+                                                                           dtype, True)
+    # extrapolation form reads k s and writes 8; ring store reads 8 and writes s
+    assert bench.kernel_rw("extrap", "form", N, 8, 8, M, False) == [(N * 64, N * 8)]
+    assert bench.kernel_rw("extrap", "update", N, 8, 8, M, False) == [(N * 8, N * 8)]
+    assert bench.mixed_roof(1.0, 0.0, 6000.0, 5000.0) == 6000.0
+    assert bench.mixed_roof(0.0, 1.0, 6000.0, 5000.0) == 5000.0
+    assert abs(bench.mixed_roof(1.0, 1.0, 6000.0, 4000.0) - 4800.0) < 1e-9
