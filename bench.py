@@ -44,7 +44,11 @@ KERNELS = {
 for _m in ("projqr", "proj_l2", "projqr_l2"):
     KERNELS[(_m, "form")] = KERNELS[("proj", "form")]
     KERNELS[(_m, "update")] = KERNELS[("proj", "update")]
+for _m in ("proj_raw", "projqr_raw"):
+    KERNELS[(_m, "form")] = ["raw_dots", "raw_solve", "raw_combine"]
+    KERNELS[(_m, "update")] = ["raw_store", "raw_apply", "raw_fin"]
 RING = ("extrap", "last", "spextrap")
+RAW = ("proj_raw", "projqr_raw")
 
 
 def kernel_names(method, call, dtype="f64"):
@@ -52,6 +56,8 @@ def kernel_names(method, call, dtype="f64"):
     stores the slot again when the solution's exponent differs from the previous one's."""
     if method in RING and call == "update" and dtype == "f16":
         return ["ring_store", "ring_fix"]
+    if method in RAW and call == "update" and dtype == "f16":
+        return ["raw_store", "raw_fix", "raw_apply", "raw_fin"]
     return KERNELS[(method, call)]
 
 
@@ -71,6 +77,12 @@ def kernel_rw(method, call, N, s, k_or_d, M, restart, faces=0, dtype="f64", fixe
     d = k_or_d
     if call == "form":
         return [(N * (d * s + 8), 0) if d > 0 else (0, 0), (0, 0), (N * d * s, N * 8)]
+    if method in RAW:
+        # store the solution; A on the stored vector fused with its Gram row against the nd
+        # solutions that stay (a full history restarts, or drops its oldest)
+        nd = d if d < M else (M - 1 if method == "projqr_raw" else 0)
+        store = [(N * 8, N * s)] + ([(N * 8, N * s) if fixed else (0, 0)] if f16 else [])
+        return store + [(N * (nd + 1) * s + faces, 0), (0, 0)]
     if restart and f16:
         # the apply pass reads x and writes A x with max |x|, |A x|; the write kernel stores the pair
         return [(N * 8 + faces, N * 8), (0, 0), (0, 0), (0, 0), (N * 16, N * 2 * s), (0, 0)]
@@ -118,6 +130,8 @@ def parse():
                    help="projection: relative rejection threshold of a new vector (<= 0: the library's "
                         "default for the storage format, 1e-6 for FP64)")
     p.add_argument("--precision-dtypes", default="f32,f16,bf16")
+    p.add_argument("--precision-methods", default="extrap,proj,proj_raw",
+                   help="methods of the reduced-precision runs (proj_raw: reduced precision only)")
     p.add_argument("--progress", action="store_true", help="print a line to stderr after every step")
     p.add_argument("--fields", choices=("one", "ins"), default="one",
                    help="ins: per step three velocity components (shift --velocity-shift) and a pressure "
@@ -648,10 +662,12 @@ def main():
     bufs = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in fields]
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
 
-    def run(dtype, steps, warmup, shadow=False):
+    def run(dtype, steps, warmup, shadow=False, methods=methods):
         """Time `steps` steps after `warmup` untimed ones; with `shadow`, an FP64
         context per method is fed the same solutions, and the guess error of the
-        reduced-precision history against it is recorded."""
+        reduced-precision history against it is recorded (the raw-solution projection,
+        which takes reduced-precision histories only, against the FP64 Gram-Schmidt form
+        with the same window rule)."""
         s = L.ELEM_BYTES[L.DTYPES[dtype]]
         ctx, xs, sh, x64 = {}, {}, {}, None
         for fi, (_, fop, _) in enumerate(fields):
@@ -663,6 +679,8 @@ def main():
                 L.guess_profile(ctx[fi, m], True)
                 xs[fi, m] = torch.zeros(N, dtype=torch.float64, device="cuda")
                 if shadow:
+                    if m in RAW:
+                        meth = L.PROJ_QR if m == "projqr_raw" else L.PROJ
                     sh[fi, m] = L.guess_create_ex(N, 1 if m == "last" else M, meth,
                                                   args.degree if m in ("extrap", "spextrap") else 0, L.F64,
                                                   args.eps_rel, fop.handle, L.stream_handle(), inner)
@@ -702,8 +720,9 @@ def main():
             L.guess_update(g, x)
             tu = L.guess_kernel_times(g)
             fixed = False
-            if dtype == "f16" and m in RING and timed:
-                fixed = L.guess_get_info(g)["update_bytes"] > 1.5 * N * (8 + s)
+            if dtype == "f16" and (m in RING or m in RAW) and timed:
+                plain = sum(kernel_bytes(m, "update", N, s, inf1["count"], M, False, faces, dtype, False))
+                fixed = L.guess_get_info(g)["update_bytes"] > plain + 0.5 * N * (8 + s)
             if shadow:
                 L.guess_update(sh[fi, m], x)
             if st != L.OK:
@@ -832,7 +851,8 @@ def main():
         prec = {}
         for dt in [d.strip() for d in args.precision_dtypes.split(",") if d.strip()]:
             try:
-                st_, ks_, wall_ = run(dt, args.precision_steps, args.warmup, shadow=True)
+                pm = [m.strip() for m in args.precision_methods.split(",") if m.strip()]
+                st_, ks_, wall_ = run(dt, args.precision_steps, args.warmup, shadow=True, methods=pm)
             except RuntimeError as e:
                 # a reduced-precision history can produce a guess PCG cannot start from
                 # (e.g. FP16 overflow); that is a result of this sweep, not a bench failure

@@ -57,7 +57,10 @@ enum {
     GUESS_PROJ = 3,   /* A-orthonormal projection, classic restart (§2, Alg. 1)     */
     GUESS_SPEXTRAP = 4, /* sparse extrapolation: m+1 of M solutions chosen by
                            column-pivoted QR (§3.3, eq. CPQRCoeffs)               */
-    GUESS_PROJ_QR = 5   /* projection, rolling window with QR update (§2, Alg. 2) */
+    GUESS_PROJ_QR = 5,  /* projection, rolling window with QR update (§2, Alg. 2) */
+    GUESS_PROJ_RAW = 6, /* projection through the Gram matrix of the stored raw
+                           solutions, classic restarts (guess_update)             */
+    GUESS_PROJ_RAW_QR = 7 /* the same with the rolling window (drop the oldest)      */
 };
 
 /* projection inner product */
@@ -143,7 +146,7 @@ typedef struct guess_opts {
     int dtype;          /* storage format of the history (GUESS_F64 ...)             */
     double eps_rel;     /* PROJ: reject if nu <= eps_rel * nu0; <= 0 selects the default
                            of the storage format: 1e-6 (F64), 1e-4 (F32), 1e-2 (F16, BF16),
-                           which grows with its unit roundoff                         */
+                           which grows with its unit roundoff; PROJ_RAW: 1e-6          */
     guess_op_t op;      /* PROJ: operator applied in guess_update when Ax == NULL    */
     void *stream;       /* hipStream_t; NULL = null stream                           */
     int inner;          /* PROJ, PROJ_QR: GUESS_INNER_A (default) or GUESS_INNER_L2  */
@@ -194,6 +197,29 @@ size_t guess_workspace_bytes(int64_t N, int M, int method, int dtype);
  * widened and accumulated in FP32 (extrapolation) or FP64 (projection).
  */
 int guess_form(guess_t g, const double *b, double *x0);
+
+/*
+ * Raw-solution projection (GUESS_PROJ_RAW, GUESS_PROJ_RAW_QR).  The guess of
+ * §2 -- the A-norm-optimal combination of the stored solutions -- computed
+ * from the stored solutions W themselves and their Gram matrix G = W^T A W
+ * (FP64, with its Cholesky factor L, on the device) instead of an
+ * A-orthonormal basis: x0 = W y with G y = W^T b; a new solution w (rounded
+ * to the storage format; FP16 as round(2^e x) with e from max |x|) is kept iff
+ * nu > eps_rel * nu0, nu^2 = w^T A w - g^T G^{-1} g, g = W^T A w, nu0^2 = w^T A w
+ * (the A-norm of its part outside the stored span, and its own).  In exact
+ * arithmetic the guesses and decisions are those of Algorithm 1 (classic
+ * restarts) and Algorithm 2 (rolling window); the basis X = W L^-T, and
+ * guess_proj_factor returns L^T (raw solutions = X R).  A reduced-precision
+ * history keeps the exact projection onto the vectors actually stored, with no
+ * normalised column whose rounding near-dependence could magnify; it needs
+ * the bound operator (applied once per update, to the stored vector) and
+ * takes no Ax.  Reduced-precision storage only (FP32, FP16, BF16; EINVAL for
+ * FP64): in FP64 the Schur complement of nearly dependent exact solutions is
+ * accurate only to u cond(G) w^T A w, far above eps_rel^2 w^T A w, while a
+ * rounded history's own rounding keeps G's condition moderate.  Default
+ * eps_rel 1e-6.  Bytes per unknown: guess 2 (d s + 8); update 8 + (d + 2) s
+ * (FP16: 8 + s more when a solution's exponent differs from the previous one).
+ */
 
 /*
  * Add the solution x of the latest solve to the history (§2: the update of
@@ -278,9 +304,9 @@ int guess_extrap_weights(int m, int k, double *beta);
 int guess_spextrap_weights(int m, int k, double *beta);
 
 /* Copy stored history vector j (PROJ: column j of X (which = 0) or B
- * (which = 1), scale applied; EXTRAP: j-th oldest stored solution, FP16
- * slots descaled) into the FP64 device vector out.  For tests and
- * checkpoints; synchronises. */
+ * (which = 1), scale applied; EXTRAP and PROJ_RAW: j-th oldest stored
+ * solution (which = 0), FP16 slots descaled) into the FP64 device vector
+ * out.  For tests and checkpoints; synchronises. */
 int guess_history_get(guess_t g, int which, int j, double *out);
 
 /*
@@ -304,7 +330,9 @@ int guess_history_raw(guess_t g, int which, int j, double *out, double *scale);
  * raw solutions are the accepted ones since the last restart (classic) or
  * the window of the last d accepted ones (rolling).  Writes *d and the d x d
  * factor row-major into R (room for GUESS_MAX_M^2 values, host memory).
- * Synchronises the context's stream.
+ * PROJ_RAW, PROJ_RAW_QR: R = L^T, L the Cholesky factor of the stored
+ * solutions' Gram matrix (the same R in exact arithmetic, the stored vectors
+ * being the raw solutions).  Synchronises the context's stream.
  */
 int guess_proj_factor(guess_t g, double *R, int *d);
 

@@ -24,10 +24,12 @@ pcg         Jacobi-preconditioned conjugate gradients
 projection  Fischer's projection: classic restarts (Algorithm 1) or the rolling
             window with its QR update (Algorithm 2), in the A inner product or
             the paper's l2 one, and the brute-force normal-equation minimiser
+rawproj     the same A-norm projection through the Gram matrix of the stored
+            (rounded) raw solutions, classic or rolling
 sequence    the time-step driver: form guess -> solve -> update
 adjoint     reference gradient of the differentiation workload
 
 Functions whose result is pinned only by self-consistency say
 "parity unpinned" in their docstring.
 """
-from . import extrap, lowprec, operator, pcg, projection, sequence, adjoint  # noqa: F401
+from . import extrap, lowprec, operator, pcg, projection, rawproj, sequence, adjoint  # noqa: F401

@@ -24,14 +24,16 @@ LIB = os.path.join(PKG, "_lib", "libguess.so")
 # the fused apply 8 % and the second Gram-Schmidt pass 3 % faster; the
 # extrapolation kernels gained nothing, so they keep the default).  The
 # projection kernels are compiled once per storage format and variant (bit 1:
-# rolling QR, bit 2: l2 inner product).
+# rolling QR, bit 2: l2 inner product), the raw-solution projection once per
+# storage format.
 _DTYPES = ["GUESS_F64", "GUESS_F32", "GUESS_F16", "GUESS_BF16"]
 _MAX_ILP = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
 UNITS = [("proj_inst.hip", f"proj_{dt[6:].lower()}_v{vf}",
           [f"-DLG_PROJ_DT={dt}", f"-DLG_PROJ_VF={vf}", *_MAX_ILP])
          for dt in _DTYPES for vf in range(4)]
+UNITS += [("rawproj_inst.hip", f"rawproj_{dt[6:].lower()}", [f"-DLG_RAW_DT={dt}", *_MAX_ILP]) for dt in _DTYPES]
 UNITS += [("pcg.hip", "pcg", [*_MAX_ILP, "-DLG_WAVES_MIN=2"])]
-UNITS += [(src, src[:-4], []) for src in ("extrap.hip", "proj.hip", "op.hip", "vec.hip", "host.hip")]
+UNITS += [(src, src[:-4], []) for src in ("extrap.hip", "proj.hip", "rawproj.hip", "op.hip", "vec.hip", "host.hip")]
 SOURCES = sorted({u[0] for u in UNITS})
 ARCH = "gfx950"
 

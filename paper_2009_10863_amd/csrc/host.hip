@@ -441,6 +441,8 @@ struct guess_ctx {
     double *w = nullptr, *part = nullptr;
     lg::ProjState *st = nullptr, *host_st = nullptr;
     int last_update_ax = 0;
+    // raw-solution projection: stored solutions in X, FP64 Gram matrix and factor in rst
+    lg::RawState *rst = nullptr, *host_rst = nullptr;
     // bookkeeping
     double form_bytes = 0.0, update_bytes = 0.0;
     // optional per-kernel timing of the most recent form / update call
@@ -456,9 +458,11 @@ static void ctx_free(guess_ctx *g) {
             (void)hipEventDestroy(g->kev.stop[i]);
         }
     if (!g->external)
-        for (void *ptr : {g->ring, g->X, g->B, (void *)g->w, (void *)g->part, (void *)g->st, (void *)g->rs})
+        for (void *ptr : {g->ring, g->X, g->B, (void *)g->w, (void *)g->part, (void *)g->st, (void *)g->rs,
+                          (void *)g->rst})
             if (ptr) (void)hipFree(ptr);
     if (g->host_st) (void)hipHostFree(g->host_st);
+    if (g->host_rst) (void)hipHostFree(g->host_rst);
     if (g->host_rs) (void)hipHostFree(g->host_rs);
     delete g;
 }
@@ -467,6 +471,7 @@ static bool ring_method(int method) {
     return method == GUESS_LAST || method == GUESS_EXTRAP || method == GUESS_SPEXTRAP;
 }
 static bool proj_method(int method) { return method == GUESS_PROJ || method == GUESS_PROJ_QR; }
+static bool raw_method(int method) { return method == GUESS_PROJ_RAW || method == GUESS_PROJ_RAW_QR; }
 
 // Device buffers of a context, in carving order; every one starts 256-byte
 // aligned (sizes rounded up to 256 bytes).
@@ -487,6 +492,10 @@ static int ctx_buffers(int64_t N, int M, int method, int dtype, size_t sizes[6])
         sizes[3] = round256((size_t)N * 8);
         sizes[4] = round256(sizeof(double) * lg::kMaxPartialBlocks * lg::kMaxDots);
         sizes[5] = round256(sizeof(lg::ProjState));
+    } else if (raw_method(method)) {
+        sizes[1] = col * M;
+        sizes[4] = round256(sizeof(double) * lg::kMaxPartialBlocks * lg::kMaxDots);
+        sizes[5] = round256(sizeof(lg::RawState));
     }
     return 1;
 }
@@ -514,6 +523,23 @@ static int ring_read_state(guess_ctx *g) {
     return GUESS_OK;
 }
 
+// Raw-solution projection: empty history, slots in order.
+static int raw_upload_state(guess_ctx *g) {
+    lg::RawState s{};
+    for (int j = 0; j < GUESS_MAX_M; ++j) s.perm[j] = j;
+    s.eps_rel = g->eps_rel;
+    *g->host_rst = s;
+    LG_HIP(hipMemcpyAsync(g->rst, g->host_rst, sizeof s, hipMemcpyHostToDevice, g->stream));
+    LG_HIP(hipStreamSynchronize(g->stream));
+    return GUESS_OK;
+}
+
+static int raw_read_state(guess_ctx *g) {
+    LG_HIP(hipMemcpyAsync(g->host_rst, g->rst, sizeof(lg::RawState), hipMemcpyDeviceToHost, g->stream));
+    LG_HIP(hipStreamSynchronize(g->stream));
+    return GUESS_OK;
+}
+
 static int proj_upload_state(guess_ctx *g) {
     lg::ProjState s{};
     s.M = g->M;
@@ -530,7 +556,9 @@ static int proj_upload_state(guess_ctx *g) {
 // normalisation of a column accepted with ratio nu/nu0 amplifies by nu0/nu;
 // the default therefore grows with the format's unit roundoff (the values
 // are the best of 1e-6 ... 1e-1 on the plane-wave sequences at 256^3).
-static double default_eps_rel(int dtype) {
+static double default_eps_rel(int dtype, int method) {
+    // the raw-solution form takes rounding into its Gram matrix; one threshold fits every format
+    if (method == GUESS_PROJ_RAW || method == GUESS_PROJ_RAW_QR) return 1e-6;
     switch (dtype) {
         case GUESS_F32: return 1e-4;
         case GUESS_F16:
@@ -545,13 +573,19 @@ extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
     int M = o->M;
     if (o->method == GUESS_LAST) M = 1;
     if (o->N < 1) return fail(GUESS_EINVAL, "guess_create: need N >= 1");
-    if (o->method < GUESS_ZERO || o->method > GUESS_PROJ_QR) return fail(GUESS_EINVAL, "guess_create: unknown method");
+    if (o->method < GUESS_ZERO || o->method > GUESS_PROJ_RAW_QR) return fail(GUESS_EINVAL, "guess_create: unknown method");
     if (o->method != GUESS_ZERO && (M < 1 || M > GUESS_MAX_M))
         return fail(GUESS_EINVAL, "guess_create: need 1 <= M <= 16");
     const int degree = o->method == GUESS_LAST ? 0 : o->degree;
     if ((o->method == GUESS_EXTRAP || o->method == GUESS_SPEXTRAP) && (degree < 0 || degree > M - 1))
         return fail(GUESS_EINVAL, "guess_create: need 0 <= degree <= M-1");
     if (esize(o->dtype) == 0) return fail(GUESS_EINVAL, "guess_create: unknown dtype");
+    // In FP64 the Schur complement nu^2 = w^T A w - g^T G^{-1} g of nearly dependent exact
+    // solutions is accurate only to u cond(G) w^T A w, far above eps_rel^2 w^T A w; the
+    // Gram-Schmidt forms (PROJ, PROJ_QR) compute nu from the remainder itself.
+    if ((o->method == GUESS_PROJ_RAW || o->method == GUESS_PROJ_RAW_QR) && o->dtype == GUESS_F64)
+        return fail(GUESS_EINVAL, "guess_create: the raw-solution projection is for reduced-precision histories; "
+                                  "FP64 histories use GUESS_PROJ / GUESS_PROJ_QR");
     if (o->inner != GUESS_INNER_A && o->inner != GUESS_INNER_L2)
         return fail(GUESS_EINVAL, "guess_create: unknown inner product");
     if (o->op && o->op->g.n != o->N) return fail(GUESS_EINVAL, "guess_create: operator size differs from N");
@@ -564,7 +598,7 @@ extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
     g->degree = degree;
     g->dtype = o->dtype;
     g->es = esize(o->dtype);
-    g->eps_rel = o->eps_rel > 0.0 ? o->eps_rel : default_eps_rel(o->dtype);
+    g->eps_rel = o->eps_rel > 0.0 ? o->eps_rel : default_eps_rel(o->dtype, o->method);
     g->inner = o->inner;
     g->vf = (o->method == GUESS_PROJ_QR ? 1 : 0) | (o->inner == GUESS_INNER_L2 ? 2 : 0);
     g->op = o->op;
@@ -618,6 +652,13 @@ extern "C" int guess_create_ex(const guess_opts *o, guess_t *out) {
         if (rc == GUESS_OK && hipHostMalloc((void **)&g->host_st, sizeof(lg::ProjState), hipHostMallocDefault) != hipSuccess)
             rc = fail(GUESS_ENOMEM, "guess_create: pinned allocation failed");
         if (rc == GUESS_OK) rc = proj_upload_state(g);
+    } else if (raw_method(g->method)) {
+        rc = alloc(&g->X, col * g->M);
+        if (rc == GUESS_OK) rc = alloc((void **)&g->part, sizeof(double) * lg::kMaxPartialBlocks * lg::kMaxDots);
+        if (rc == GUESS_OK) rc = alloc((void **)&g->rst, sizeof(lg::RawState));
+        if (rc == GUESS_OK && hipHostMalloc((void **)&g->host_rst, sizeof(lg::RawState), hipHostMallocDefault) != hipSuccess)
+            rc = fail(GUESS_ENOMEM, "guess_create: pinned allocation failed");
+        if (rc == GUESS_OK) rc = raw_upload_state(g);
     }
     if (rc != GUESS_OK) {
         ctx_free(g);
@@ -663,6 +704,19 @@ static int ring_weights(guess_ctx *g, int m, int k, const double **out) {
     }
     *out = g->beta[k][m];
     return GUESS_OK;
+}
+
+static lg::RawBufs raw_bufs(guess_ctx *g) {
+    lg::RawBufs p;
+    p.W = g->X;
+    p.part = g->part;
+    p.st = g->rst;
+    p.N = g->N;
+    p.ld = g->ld;
+    p.M = g->M;
+    p.qr = g->method == GUESS_PROJ_RAW_QR ? 1 : 0;
+    p.dtype = g->dtype;
+    return p;
 }
 
 static lg::ProjBufs proj_bufs(guess_ctx *g) {
@@ -729,6 +783,15 @@ extern "C" int guess_form(guess_t g, const double *b, double *x0) {
             g->form_bytes = -1.0;  // known after the device reports d
             return check_launch("guess_form");
         }
+        case GUESS_PROJ_RAW:
+        case GUESS_PROJ_RAW_QR: {
+            if (!b) return fail(GUESS_EINVAL, "guess_form: projection needs b");
+            if (b == x0) return fail(GUESS_EINVAL, "guess_form: b and x0 must not alias");
+            if (!aligned16(b)) return fail(GUESS_EINVAL, "guess_form: b must be 16-byte aligned");
+            LG_TRY(lg::launch_raw_form(raw_bufs(g), b, x0, g->stream, g->prof ? &g->kev : nullptr));
+            g->form_bytes = -1.0;
+            return check_launch("guess_form");
+        }
     }
     return fail(GUESS_EINVAL, "guess_form: bad method");
 }
@@ -766,6 +829,15 @@ extern "C" int guess_update(guess_t g, const double *x, const double *Ax) {
             LG_TRY(lg::launch_proj_update(proj_bufs(g), g->op ? &g->op->g : nullptr, x, Ax, g->stream,
                                           g->prof ? &g->kev : nullptr));
             g->last_update_ax = Ax != nullptr;
+            g->update_bytes = -1.0;
+            return check_launch("guess_update");
+        }
+        case GUESS_PROJ_RAW:
+        case GUESS_PROJ_RAW_QR: {
+            if (!g->op) return fail(GUESS_EINVAL, "guess_update: the raw-solution projection needs an operator");
+            if (Ax) return fail(GUESS_EINVAL, "guess_update: the raw-solution projection applies A to the stored "
+                                              "vector itself; pass Ax = NULL");
+            LG_TRY(lg::launch_raw_update(raw_bufs(g), g->op->g, x, g->stream, g->prof ? &g->kev : nullptr));
             g->update_bytes = -1.0;
             return check_launch("guess_update");
         }
@@ -828,6 +900,31 @@ extern "C" int guess_get_info(guess_t g, guess_info *info) {
                                              (double)G.nx * G.ny * (G.nz + 1));
             }
         }
+    } else if (raw_method(g->method)) {
+        LG_TRY(raw_read_state(g));
+        const lg::RawState &s = *g->host_rst;
+        info->count = s.d;
+        info->last_accepted = s.last_accepted;
+        info->restarts = s.restarts;
+        info->rejects = s.rejects;
+        info->nonfinite = s.nonfinite;
+        info->nu = s.nu;
+        info->nu0 = s.nu0;
+        info->drops = s.drops;
+        const double N = (double)g->N, es = g->es;
+        if (g->form_bytes < 0) info->form_bytes = s.form_d == 0 ? 8.0 * N : 2.0 * N * (s.form_d * es + 8.0);
+        if (g->update_bytes < 0) {
+            // store 8 + s (FP16: twice when the exponent changed); apply: the stored vector and
+            // the columns of the Gram row, (nd + 1) s
+            const int d = s.upd_d;
+            const int nd = d >= g->M ? (g->method == GUESS_PROJ_RAW_QR ? g->M - 1 : 0) : d;
+            info->update_bytes = N * (8.0 + es) * (s.fixed && g->dtype == GUESS_F16 ? 2.0 : 1.0) + N * (nd + 1) * es;
+            if (g->op && g->op->g.kx) {
+                const lg::Grid &G = g->op->g;
+                info->update_bytes += 8.0 * ((double)(G.nx + 1) * G.ny * G.nz + (double)G.nx * (G.ny + 1) * G.nz +
+                                             (double)G.nx * G.ny * (G.nz + 1));
+            }
+        }
     } else {
         LG_HIP(hipStreamSynchronize(g->stream));
         info->count = g->count;
@@ -853,6 +950,12 @@ extern "C" int guess_reset(guess_t g) {
         g->host_st->mode = 0;
         g->host_st->drop = 0;
         LG_HIP(hipMemcpyAsync(g->st, g->host_st, sizeof(lg::ProjState), hipMemcpyHostToDevice, g->stream));
+        LG_HIP(hipStreamSynchronize(g->stream));
+    } else if (raw_method(g->method)) {
+        LG_HIP(hipStreamSynchronize(g->stream));
+        LG_TRY(raw_read_state(g));
+        g->host_rst->d = 0;
+        LG_HIP(hipMemcpyAsync(g->rst, g->host_rst, sizeof(lg::RawState), hipMemcpyHostToDevice, g->stream));
         LG_HIP(hipStreamSynchronize(g->stream));
     }
     return GUESS_OK;
@@ -906,6 +1009,14 @@ static int history_vector(guess_t g, int which, int j, const char *fn, const voi
         }
         return GUESS_OK;
     }
+    if (raw_method(g->method)) {
+        LG_TRY(raw_read_state(g));
+        if (j < 0 || j >= g->host_rst->d || which != 0) return fail(GUESS_EINVAL, std::string(fn) + ": index out of range");
+        const int slot = g->host_rst->perm[j];
+        *src = (const char *)g->X + (size_t)slot * g->ld * g->es;
+        *scale = std::ldexp(1.0, -g->host_rst->exps[slot]);
+        return GUESS_OK;
+    }
     if (proj_method(g->method)) {
         LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));
         LG_HIP(hipStreamSynchronize(g->stream));
@@ -941,6 +1052,15 @@ extern "C" int guess_history_raw(guess_t g, int which, int j, double *out, doubl
 
 extern "C" int guess_proj_factor(guess_t g, double *R, int *d) {
     if (!g || !R || !d) return fail(GUESS_EINVAL, "guess_proj_factor: NULL argument");
+    if (raw_method(g->method)) {
+        // R = L^T: raw solutions = X R with X = W L^-T A-orthonormal
+        LG_TRY(raw_read_state(g));
+        const int n = g->host_rst->d;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) R[i * n + j] = j >= i ? g->host_rst->L[j][i] : 0.0;
+        *d = n;
+        return GUESS_OK;
+    }
     if (!proj_method(g->method)) return fail(GUESS_EINVAL, "guess_proj_factor: not a projection context");
     LG_HIP(hipMemcpyAsync(g->host_st, g->st, sizeof(lg::ProjState), hipMemcpyDeviceToHost, g->stream));
     LG_HIP(hipStreamSynchronize(g->stream));

@@ -92,6 +92,35 @@ int launch_ring_store(int dtype, const double *x, void *slot, int64_t N, hipStre
 int launch_fill_zero(double *x, int64_t N, hipStream_t s);
 int launch_widen(int dtype, const void *src, double scale, double *out, int64_t N, hipStream_t s);
 
+// Device-resident state of a raw-solution projection history (rawproj_impl.h):
+// the stored solutions' slots, their Gram matrix G = W^T A W and its Cholesky
+// factor L (FP64, oldest solution first), FP16 exponents.
+struct RawState {
+    int d;                       // stored solutions
+    int last_accepted, restarts, rejects, nonfinite, drops, form_d, upd_d;
+    int perm[GUESS_MAX_M];       // slot of the j-th oldest stored solution
+    int exps[GUESS_MAX_M];       // FP16: exponent of each slot (stored = round(2^e x)); else 0
+    int e_guess;                 // FP16: exponent the next store tries first
+    int e_used;                  // FP16: exponent the store of this update used
+    int new_exp;                 // FP16: exponent of this update's solution
+    int fixed;                   // FP16: this update stored its slot twice
+    unsigned long long maxbits;  // FP16: bits of max |x| of the store in flight
+    double eps_rel, nu0, nu;
+    double G[GUESS_MAX_M][GUESS_MAX_M];
+    double L[GUESS_MAX_M][GUESS_MAX_M];
+    double gamma[GUESS_MAX_M];   // guess: x0 = sum_j gamma[j] * stored column perm[j]
+};
+
+struct RawBufs {
+    void *W;                 // M slots of N elements of the storage type
+    double *part;            // per-workgroup partial sums
+    RawState *st;
+    int64_t N, ld;
+    int M, qr, dtype;
+};
+int launch_raw_form(const RawBufs &p, const double *b, double *x0, hipStream_t s, KEvents *ev = nullptr);
+int launch_raw_update(const RawBufs &p, const Grid &g, const double *x, hipStream_t s, KEvents *ev = nullptr);
+
 // ---- projection (proj.hip)
 struct ProjBufs {
     void *X;                 // M stored columns of X, each N elements of the storage type

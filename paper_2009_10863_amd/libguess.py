@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LIBGUESS_SO") or os.path.join(_HERE, "_lib", "libguess.so")
 
 # ---------------------------------------------------------------- constants
-ZERO, LAST, EXTRAP, PROJ, SPEXTRAP, PROJ_QR = 0, 1, 2, 3, 4, 5
+ZERO, LAST, EXTRAP, PROJ, SPEXTRAP, PROJ_QR, PROJ_RAW, PROJ_RAW_QR = 0, 1, 2, 3, 4, 5, 6, 7
 INNER_A, INNER_L2 = 0, 1
 F64, F32, F16, BF16 = 0, 1, 2, 3
 ROOF_COPY, ROOF_READ, ROOF_WRITE = 0, 1, 2
@@ -24,9 +24,9 @@ OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ENONFINITE = 0, -1, -2, -3, -4, 
 STOP_RHS, STOP_INITRESID = 0, 1
 MAX_M = 16
 METHODS = {"zero": ZERO, "last": LAST, "extrap": EXTRAP, "proj": PROJ, "spextrap": SPEXTRAP,
-           "projqr": PROJ_QR}
+           "projqr": PROJ_QR, "proj_raw": PROJ_RAW, "projqr_raw": PROJ_RAW_QR}
 # method names with an inner-product suffix: "proj_l2", "projqr_l2"
-PROJ_METHODS = ("proj", "projqr", "proj_l2", "projqr_l2")
+PROJ_METHODS = ("proj", "projqr", "proj_l2", "projqr_l2", "proj_raw", "projqr_raw")
 
 
 def parse_method(name: str):
