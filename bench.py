@@ -246,7 +246,9 @@ def cpu_baseline(args, s_bytes):
     `cpu_steps` steps of EXTRAP(m, M) and PROJ(M) form+update are timed on one host thread
     and, from the same state, on all host cores (BLAS threads; NumPy's elementwise passes
     stay on one).  The oracle's own operator is applied once per projection update.
-    Reported in the same algorithmic GB/s as the GPU value.
+    Reported in the same algorithmic GB/s as the GPU value.  The oracle's guesses at the last
+    two steps also serve as the FP64 reference of the library's guess error per history format
+    (`guess_rel_err_vs_oracle`).
     """
     import numpy as np
     from threadpoolctl import threadpool_limits
@@ -285,7 +287,11 @@ def _cpu_baseline(args, np, cores, threadpool_limits):
     setup_s = time.perf_counter() - t_setup
     state = copy.deepcopy((e, P))
 
-    def timed(threads):
+    last = M + args.cpu_steps
+    sample_steps = [s for s in (last - 1, last) if s > M]
+    sampled = {}     # step -> (EXTRAP guess, PROJ guess) of the oracle
+
+    def timed(threads, keep=False):
         ee, PP = copy.deepcopy(state)
         nbytes, secs = 0.0, 0.0
         with threadpool_limits(limits=threads):
@@ -293,21 +299,24 @@ def _cpu_baseline(args, np, cores, threadpool_limits):
                 a = amps(step)
                 b, x = a @ F, a @ U
                 t0 = time.perf_counter()
-                ee.form(N=N)
+                ge = ee.form(N=N)
                 ee.update(x)
                 secs += time.perf_counter() - t0
                 nbytes += N * (M * 8 + 8) + N * 16
                 d = PP.d
                 t0 = time.perf_counter()
-                PP.form(b)
+                gp = PP.form(b)
                 PP.update(x)
                 secs += time.perf_counter() - t0
                 restart = d == 0 or d >= M
                 nbytes += 2 * N * (d * 8 + 8) + (N * (8 + 16) if restart else N * (5 * d * 8 + 16 + 40))
+                if keep and step in sample_steps:
+                    sampled[step] = (ge, gp)
         return nbytes / secs / 1e9, secs, PP.d
 
     one, one_s, d_end = timed(1)
-    allc, all_s, _ = timed(cores)
+    allc, all_s, _ = timed(cores, keep=True)
+    vs_oracle = _precision_vs_oracle(args, np, n, M, m, F, U, amps, sampled) if args.precision_steps > 0 else None
     # the whole small sequence (32^3, 4 plane waves, 50 steps, dt = 0.01): guess -> PCG -> update
     n1 = 32
     op1 = oop.Operator(n1)
@@ -329,10 +338,59 @@ def _cpu_baseline(args, np, cores, threadpool_limits):
                   f"solutions; FP64 NumPy with {cores} BLAS threads, {all_s:.1f} s timed "
                   f"(setup {setup_s:.0f} s); projection history at d = {d_end} at the end",
         "one_thread": {"value": one, "unit": "GB/s", "cores": 1, "timed_s": round(one_s, 2)},
+        "guess_rel_err_vs_oracle": vs_oracle,
         "small_sequence": {"workload": f"{n1}^3, 4 plane-wave modes, 50 steps, dt = 0.01, M = {M}, "
                                        f"EXTRAP({m},{M}) / PROJ({M}), guess -> PCG -> update, one thread",
                            "methods": seq},
     }
+
+
+def _precision_vs_oracle(args, np, n, M, m, F, U, amps, sampled):
+    """Guess error of the library against the FP64 oracle at the sampled steps of the
+    cpu_baseline sequence (the same exact solutions and right-hand sides): one library context
+    per history format and method is fed the whole sequence, and at each sampled step its guess
+    x0 is compared with the oracle's FP64 guess g as max|x0 - g| / max|g| (EXTRAP(m, M) against
+    the oracle's extrapolation, every projection form against its FP64 A-norm projection)."""
+    import torch
+
+    from paper_2009_10863_amd import libguess as L
+
+    N = n ** 3
+    dts = ["f64"] + [d.strip() for d in args.precision_dtypes.split(",") if d.strip() and d.strip() != "f64"]
+    A = L.guess_op_create(n, n, n, float((n + 1) ** 2), 10.0, None)
+    ctx = {}
+    try:
+        for dt in dts:
+            for name in ("extrap", "proj", "proj_raw"):
+                if name == "proj_raw" and dt == "f64":
+                    continue
+                meth, _ = L.parse_method(name)
+                ctx[dt, name] = L.guess_create_ex(N, M, meth, m if name == "extrap" else 0, L.DTYPES[dt],
+                                                  args.eps_rel, A)
+        bg = torch.empty(N, dtype=torch.float64, device="cuda")
+        xg, x0 = torch.empty_like(bg), torch.empty_like(bg)
+        err = {dt: {} for dt in dts}
+        for step in range(1, max(sampled) + 1 if sampled else 0):
+            a = amps(step)
+            bg.copy_(torch.from_numpy(a @ F))
+            xg.copy_(torch.from_numpy(a @ U))
+            refs = None
+            if step in sampled:
+                refs = [torch.from_numpy(v).to("cuda") for v in sampled[step]]
+            for (dt, name), g in ctx.items():
+                if refs is not None:
+                    L.guess_form(g, bg, x0)
+                    ref = refs[0] if name == "extrap" else refs[1]
+                    e = float((x0 - ref).abs().max() / ref.abs().max())
+                    err[dt].setdefault(name, []).append(e)
+                L.guess_update(g, xg)
+        torch.cuda.synchronize()
+    finally:
+        for g in ctx.values():
+            L.guess_destroy(g)
+        L.guess_op_destroy(A)
+    return {"steps": sorted(sampled), "reference": "oracle FP64 EXTRAP / PROJ (A-norm, classic) guesses",
+            "dtypes": err}
 
 
 def isolated(args, L):

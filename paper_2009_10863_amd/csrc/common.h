@@ -17,8 +17,11 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
 #ifndef LG_WAVES_MIN
 #define LG_WAVES_MIN 1
 #endif
+#ifndef LG_WAVES_MAX
+#define LG_WAVES_MAX 4
+#endif
 #define LG_REDUCE_KERNEL \
-    __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LG_WAVES_MIN, 4)))
+    __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LG_WAVES_MIN, LG_WAVES_MAX)))
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxPartialBlocks = 2048;
 constexpr int kMaxDots = 2 * GUESS_MAX_M + 4;

@@ -131,19 +131,24 @@ __device__ __forceinline__ double q_var(const Grid &g, double uc, double kw, dou
 }
 
 // Sweep the wave's work items.  U: operand access (u(q), u.two(q) as in
-// stencil.h).  f(c, e, ua, ub, au) is called once per chunk with its chunk
-// index c (as in common.h), the flat index e of its first pair, the centre
-// values of both pairs and A u at the chunk's four elements.  VAR: variable
+// stencil.h).  pf(c) loads whatever the chunk's work needs besides the
+// stencil (other vectors at chunk c) and returns it; f(c, e, ua, ub, au, pre)
+// is called once per chunk with its chunk index c (as in common.h), the flat
+// index e of its first pair, the centre values of both pairs, A u at the
+// chunk's four elements and pf's result for that chunk.  The sweep issues
+// pf for plane z+1 together with that plane's operand loads, one plane ahead
+// of f, so that those loads overlap the current plane's work.  VAR: variable
 // coefficient (face arrays of the Grid; the z-faces shared by consecutive
 // planes are loaded once).
-template <bool VAR, class U, class F>
-__device__ __forceinline__ void march_sweep(const Grid &g, const March &m, const U &u, F &&f) {
+template <bool VAR, class U, class PF, class F>
+__device__ __forceinline__ void march_sweep_pf(const Grid &g, const March &m, const U &u, PF &&pf, F &&f) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwg = gridDim.x;
     const int lb = nwg % kXcds == 0 ? (int)(blockIdx.x % kXcds) * (nwg / kXcds) + (int)(blockIdx.x / kXcds)
                                     : (int)blockIdx.x;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int64_t nxy = g.nxy;
+    const int64_t cstep = (int64_t)m.tp * 64;     // chunks per plane
     for (int item = lb * kWaves + wave; item < m.items; item += nwg * kWaves) {
         const int tau = item % m.tp, zr = item / m.tp;
         const int z0 = (int)((int64_t)zr * nz / m.nr);
@@ -158,16 +163,20 @@ __device__ __forceinline__ void march_sweep(const Grid &g, const March &m, const
         const int64_t eprev = z0 > 0 ? ea - nxy : ea;
         R2 pa_prev = sel2(z0 > 0, u.two(eprev)), pb_prev = sel2(z0 > 0, u.two(eprev + 128));
         R2 pa = u.two(ea), pb = u.two(ea + 128);
+        auto pre = pf(c);
         // bottom z-faces of plane z0 (face index f = z: kz[(f*ny + j)*nx + i] = kz[e])
         R2 kba{{0.0, 0.0}}, kbb{{0.0, 0.0}};
         if constexpr (VAR) {
             kba = ld2(g.kz, ea);
             kbb = ld2(g.kz, ea + 128);
         }
-        for (int z = z0; z < z1; ++z, ea += nxy, c += (int64_t)m.tp * 64) {
+        for (int z = z0; z < z1; ++z, ea += nxy, c += cstep) {
             const bool ht = z + 1 < nz;
             const int64_t enext = ht ? ea + nxy : ea;
             const R2 pa_next = sel2(ht, u.two(enext)), pb_next = sel2(ht, u.two(enext + 128));
+            // the next plane's other data (the current chunk again on the range's last plane,
+            // so every load stays inside the vectors)
+            const auto pre_next = pf(z + 1 < z1 ? c + cstep : c);
             const R2 sa = sel2(hsa, u.two(hsa ? ea - nx : ea)), na = sel2(hna, u.two(hna ? ea + nx : ea));
             const R2 sb = sel2(hsb, u.two(hsb ? ea + 128 - nx : ea + 128));
             const R2 nb = sel2(hnb, u.two(hnb ? ea + 128 + nx : ea + 128));
@@ -211,13 +220,21 @@ __device__ __forceinline__ void march_sweep(const Grid &g, const March &m, const
                 kba = kta;
                 kbb = ktb;
             }
-            f(c, ea, pa, pb, au);
+            f(c, ea, pa, pb, au, pre);
+            pre = pre_next;
             pa_prev = pa;
             pb_prev = pb;
             pa = pa_next;
             pb = pb_next;
         }
     }
+}
+
+// The sweep without other data: f(c, e, ua, ub, au).
+template <bool VAR, class U, class F>
+__device__ __forceinline__ void march_sweep(const Grid &g, const March &m, const U &u, F &&f) {
+    march_sweep_pf<VAR>(g, m, u, [](int64_t) { return 0; },
+                        [&](int64_t c, int64_t e, const R2 &pa, const R2 &pb, const R4 &au, int) { f(c, e, pa, pb, au); });
 }
 
 }  // namespace lg

@@ -303,10 +303,19 @@ LG_REDUCE_KERNEL void proj_apply_march_kernel(ProjArgs a, Grid g, March m, const
         double acc[ND];
 #pragma unroll
         for (int j = 0; j < ND; ++j) acc[j] = 0.0;
-        march_sweep<VAR>(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &pa, const R2 &pb, const R4 &au) {
-            V4 xc[D];
+        // the stored columns of the chunk, fetched one plane ahead
+        struct Cols {
+            V4 v[D];
+        };
+        auto pf = [&](int64_t c) {
+            Cols cl;
 #pragma unroll
-            for (int j = 0; j < D; ++j) xc[j] = load4<DT>(colp<DT>(C, a.ld, j), c);
+            for (int j = 0; j < D; ++j) cl.v[j] = load4<DT>(colp<DT>(C, a.ld, j), c);
+            return cl;
+        };
+        march_sweep_pf<VAR>(g, m, VecU{x}, pf, [&](int64_t c, int64_t, const R2 &pa, const R2 &pb, const R4 &au,
+                                                    const Cols &cl) {
+            const V4 *xc = cl.v;
             const V4 xv{{pa.v[0], pa.v[1], pb.v[0], pb.v[1]}};
             const V4 wv{{au.v[0], au.v[1], au.v[2], au.v[3]}};
             store4<GUESS_F64>(a.w, c, wv);

@@ -210,10 +210,19 @@ LG_REDUCE_KERNEL void raw_apply_march_kernel(RawArgs a, Grid g, March m) {
         double acc[D + 1];
 #pragma unroll
         for (int j = 0; j <= D; ++j) acc[j] = 0.0;
-        march_sweep<VAR>(g, m, u, [&](int64_t c, int64_t, const R2 &pa, const R2 &pb, const R4 &aw) {
-            V4 wc[D > 0 ? D : 1];
+        // the Gram row's columns at the chunk, fetched one plane ahead
+        struct Cols {
+            V4 v[D > 0 ? D : 1];
+        };
+        auto pf = [&](int64_t c) {
+            Cols cl;
 #pragma unroll
-            for (int j = 0; j < D; ++j) wc[j] = load4<DT>(col[j], c);
+            for (int j = 0; j < D; ++j) cl.v[j] = load4<DT>(col[j], c);
+            return cl;
+        };
+        march_sweep_pf<VAR>(g, m, u, pf, [&](int64_t c, int64_t, const R2 &pa, const R2 &pb, const R4 &aw,
+                                             const Cols &cl) {
+            const V4 *wc = cl.v;
             const double uv[4] = {pa.v[0], pa.v[1], pb.v[0], pb.v[1]};
 #pragma unroll
             for (int e = 0; e < 4; ++e) acc[D] = __builtin_fma(uv[e], aw.v[e], acc[D]);

@@ -199,3 +199,71 @@ def test_projection_variants_256_m8_properties(lib, method):
     finally:
         L.guess_destroy(g)
         L.guess_op_destroy(A)
+
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
+def test_proj_256_lowprec_replay(lib, dtype):
+    """Reduced-precision PROJ(8) at the benchmark's size against the oracle: seven random
+    solutions of growing magnitude and random right-hand sides.  After every update the newest
+    stored column equals the oracle's bit for bit, except where the two FP64 remainders round
+    to different neighbours of the format (a difference within one unit of the format plus
+    64 u times the raw pair in stored units; at most 1e-6 of the values); the oracle then takes
+    the library's stored history, so every guess is compared from identical states and held
+    to 1e-12 relative -- the per-format guess error against the oracle at 256^3."""
+    import torch
+
+    from proj_replay import resync
+
+    announce(f"proj 256^3 M=8 {dtype} random replay")
+    L = lib
+    M, T = 8, 7
+    A = L.guess_op_create(n, n, n, float((n + 1) ** 2), 10.0, None)
+    g = L.guess_create_ex(N, M, L.PROJ, 0, L.DTYPES[dtype], 1e-6, A)
+    Aop = op.Operator(n)
+    ref = Projection(M, Aop, 1e-6, dtype, "classic", "A")
+    x0 = torch.empty(N, dtype=torch.float64, device="cuda")
+    buf = torch.empty(N, dtype=torch.float64, device="cuda")
+    u = lowprec.UNIT_ROUNDOFF[dtype]
+    rng = np.random.default_rng(18)
+    flips, worst = 0, 0.0
+    try:
+        for s in range(T):
+            b = rng.standard_normal(N)
+            x = rng.standard_normal(N) * (1.0 + 0.5 * s)
+            L.guess_form(g, dev(b), x0)
+            want = ref.form(b)
+            if s > 0:
+                err = rel_inf(host(x0), want)
+                worst = max(worst, err)
+                assert err <= 1e-12, (s, err)
+            L.guess_update(g, dev(x))
+            ref.update(x)
+            info = L.guess_get_info(g)
+            assert info["count"] == ref.d and info["last_accepted"] == 1
+            raw = []
+            for j in range(ref.d):
+                sx = L.guess_history_raw(g, 0, j, buf)
+                xs = host(buf).copy()
+                L.guess_history_raw(g, 1, j, buf)
+                raw.append((xs, host(buf).copy(), sx))
+            xs, bs, sc = raw[-1]
+            j = ref.d - 1
+            assert abs(sc - ref.sig[j]) <= 1e-13 * ref.sig[j]
+            xmax = max(float(np.max(np.abs(x))), float(np.max(np.abs(Aop(x)))))
+            for got, wcol in ((xs, ref.S[j]), (bs, ref.T[j])):
+                diff = got.view(np.uint64) != wcol.view(np.uint64)
+                if diff.any():
+                    mag = max(float(np.max(np.abs(wcol))), xmax / (sc * info["nu"]))
+                    dv = np.abs(got[diff] - wcol[diff])
+                    assert np.all(dv <= 2 * u * np.abs(wcol[diff]) + 64 * 2.0 ** -53 * mag), (s, int(diff.sum()))
+                    flips += int(diff.sum())
+            if dtype == "f16":
+                assert np.max(np.abs(xs)) <= 2 ** 15 and np.max(np.abs(bs)) <= 2 ** 15
+            resync(L, g, ref, raw)
+    finally:
+        L.guess_destroy(g)
+        L.guess_op_destroy(A)
+    print(f"[replay] proj {dtype} 256^3: {T} steps, {flips} of {T * 2 * N} stored values differ, "
+          f"largest guess error {worst:.2e}", flush=True)
+    assert flips <= 1e-6 * T * 2 * N
