@@ -118,7 +118,7 @@ struct guess_op {
     lg::Grid g{};
     hipStream_t stream = nullptr;
     double *kx = nullptr, *ky = nullptr, *kz = nullptr, *dinv = nullptr;
-    double *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
+    double *r = nullptr, *p[3] = {nullptr, nullptr, nullptr}, *q = nullptr;   // p_k in p[k % 3]
     double *part_a = nullptr, *part_b = nullptr;  // per-workgroup partial sums of the two PCG kernels
     lg::PcgState *st = nullptr;
     lg::PcgState *host_st = nullptr;  // pinned
@@ -127,7 +127,7 @@ struct guess_op {
 static void op_free(guess_op *A) {
     if (!A) return;
     for (void *ptr : {(void *)A->kx, (void *)A->ky, (void *)A->kz, (void *)A->dinv, (void *)A->r,
-                      (void *)A->p[0], (void *)A->p[1], (void *)A->q, (void *)A->part_a, (void *)A->part_b,
+                      (void *)A->p[0], (void *)A->p[1], (void *)A->p[2], (void *)A->q, (void *)A->part_a, (void *)A->part_b,
                       (void *)A->st})
         if (ptr) (void)hipFree(ptr);
     if (A->host_st) (void)hipHostFree(A->host_st);
@@ -168,6 +168,7 @@ extern "C" int guess_op_create(int nx, int ny, int nz, double inv_h2, double shi
     if (rc == GUESS_OK) rc = alloc((void **)&A->r, n * 8);
     if (rc == GUESS_OK) rc = alloc((void **)&A->p[0], n * 8);
     if (rc == GUESS_OK) rc = alloc((void **)&A->p[1], n * 8);
+    if (rc == GUESS_OK) rc = alloc((void **)&A->p[2], n * 8);
     if (rc == GUESS_OK) rc = alloc((void **)&A->q, n * 8);
     if (rc == GUESS_OK) rc = alloc((void **)&A->part_a, sizeof(double) * lg::kMaxPartialBlocks);
     if (rc == GUESS_OK) rc = alloc((void **)&A->part_b, sizeof(double) * lg::kMaxPartialBlocks * 3);
@@ -260,10 +261,10 @@ extern "C" int pcg_solve_ex(guess_op_t A, const double *b, double *x, double rto
         lg::launch_pcg_check(A->g, A->part_b, A->st, k, rtol, s);
         LG_TRY(check_launch("pcg_check"));
     }
-    // x += alpha p of the last iteration unless a later pcg_a applied it
+    // the x updates of the last iterations unless a later pcg_a applied them
     // (a no-op on the device when nothing is pending)
     if (k > 1) {
-        lg::launch_pcg_finish(A->g, x, A->p[(k - 1) & 1], A->st, s);
+        lg::launch_pcg_finish(A->g, x, A->p, A->st, s);
         LG_TRY(check_launch("pcg_finish"));
     }
     LG_TRY(read_state());

@@ -76,11 +76,13 @@ struct RingState {
 // Device-resident state of a PCG solve (rho of iteration k in rho[k & 1]).
 struct PcgState {
     double rho[2];
-    double alpha, rr, bb, rr0, thresh;
+    double alpha[2];        // alpha_k of iteration k at [k & 1]
+    double rr, bb, rr0, thresh;
     int it;
     int converged;          // 0, or the iteration k whose stop test (on r_{k-1}) passed
     int breakdown, rule;
-    int x_pending;          // x still lacks alpha_k p_k of the last completed iteration
+    int x_last;             // last completed iteration (alpha_k known)
+    int x_pending;          // x still lacks the updates of x_last and, if x_last is even, x_last - 1
 };
 
 // ---- extrapolation (extrap.hip)
@@ -143,10 +145,10 @@ int launch_build_faces(Grid &g, const double *kappa, double *kx, double *ky, dou
 int launch_op_apply(const Grid &g, const double *x, double *y, hipStream_t s);
 int launch_pcg_init(const Grid &g, const double *b, const double *x, double *r, double *part_b,
                     hipStream_t s);
-int launch_pcg_iter(const Grid &g, double *x, double *r, double *const p[2], double *q, double *part_a,
+int launch_pcg_iter(const Grid &g, double *x, double *r, double *const p[3], double *q, double *part_a,
                     double *part_b, PcgState *st, int k, double rtol, hipStream_t s);
 int launch_pcg_check(const Grid &g, const double *part_b, PcgState *st, int k, double rtol, hipStream_t s);
-int launch_pcg_finish(const Grid &g, double *x, const double *p, PcgState *st, hipStream_t s);
+int launch_pcg_finish(const Grid &g, double *x, double *const p[3], PcgState *st, hipStream_t s);
 int pcg_grid(const Grid &g);
 
 // ---- vectors and workload (vec.hip)

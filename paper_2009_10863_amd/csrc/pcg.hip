@@ -59,6 +59,21 @@ __device__ __forceinline__ V4 dinv4(const Grid &g, int64_t c) {
     else return V4{{g.dinv_const, g.dinv_const, g.dinv_const, g.dinv_const}};
 }
 
+// q = A p is written by pcg_a and read once by the pcg_b that follows; unlike the
+// other vectors it goes through the caches with ordinary stores and loads (a
+// PCG iteration at 256^3 measured 1.8 % faster than with non-temporal ones,
+// which stay the rule for x, r and p: there cached accesses were slower).
+__device__ __forceinline__ void store_q(double *q, int64_t c, const V4 &v) {
+    const int64_t e = chunk_elem(c);
+    *reinterpret_cast<d2 *>(q + e) = d2{v.v[0], v.v[1]};
+    *reinterpret_cast<d2 *>(q + e + 128) = d2{v.v[2], v.v[3]};
+}
+__device__ __forceinline__ V4 load_q(const double *q, int64_t c) {
+    const int64_t e = chunk_elem(c);
+    const d2 a = *reinterpret_cast<const d2 *>(q + e), b = *reinterpret_cast<const d2 *>(q + e + 128);
+    return V4{{a.x, a.y, b.x, b.y}};
+}
+
 // The next search direction as a stencil operand: p = D^{-1} r + beta p_old
 // (first iteration: p = D^{-1} r), evaluated wherever the stencil reads it.
 template <bool VAR>
@@ -156,36 +171,61 @@ __device__ __forceinline__ bool pcg_a_begin(const double *part_b, int nb, PcgSta
     return true;
 }
 
-// x += alpha p over the whole vector (the deferred update when the solve
-// stops in pcg_a, and pcg_finish).
-__device__ __forceinline__ void x_update_all(const Grid &g, double *__restrict__ x, const double *__restrict__ p,
-                                             double alpha) {
+// The deferred x updates over the whole vector: x += a1 p1, then (TWO)
+// x += a2 p2, the older iteration first (the stop in pcg_a, and pcg_finish).
+template <bool TWO>
+__device__ __forceinline__ void x_update_all(const Grid &g, double *__restrict__ x, const double *__restrict__ p1,
+                                             double a1, const double *__restrict__ p2, double a2) {
     const int64_t nc = nchunks(g.n), stride = (int64_t)gridDim.x * kBlock;
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
         V4 xv = load4<GUESS_F64>(x, c);
-        const V4 pv = load4<GUESS_F64>(p, c);
+        const V4 pv = load4<GUESS_F64>(p1, c);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) xv.v[e] = __builtin_fma(alpha, pv.v[e], xv.v[e]);
+        for (int e = 0; e < 4; ++e) xv.v[e] = __builtin_fma(a1, pv.v[e], xv.v[e]);
+        if constexpr (TWO) {
+            const V4 pw = load4<GUESS_F64>(p2, c);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) xv.v[e] = __builtin_fma(a2, pw.v[e], xv.v[e]);
+        }
         store4<GUESS_F64>(x, c, xv);
     }
     if (blockIdx.x == 0 && threadIdx.x < tail_count(g.n)) {
         const int64_t t = tail_start(g.n) + threadIdx.x;
-        x[t] = __builtin_fma(alpha, p[t], x[t]);
+        double xt = __builtin_fma(a1, p1[t], x[t]);
+        if constexpr (TWO) xt = __builtin_fma(a2, p2[t], xt);
+        x[t] = xt;
     }
 }
 
-template <bool VAR, bool AL>
+// Iteration k's start in both forms of pcg_a when the solve stops there:
+// apply what x still lacks (the updates of iterations k-2 and k-1 for odd
+// k >= 3, of k-1 for even k, nothing for k = 1).
+template <bool XU>
+__device__ __forceinline__ void x_update_at_stop(const Grid &g, double *x, const double *pold2, const double *pold,
+                                                 PcgState *st, int k) {
+    if constexpr (XU) {
+        x_update_all<true>(g, x, pold2, st->alpha[k & 1], pold, st->alpha[(k - 1) & 1]);
+    } else if (k > 1) {
+        x_update_all<false>(g, x, pold, st->alpha[(k - 1) & 1], nullptr, 0.0);
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->x_pending = 0;
+    }
+}
+
+// XU (odd k >= 3): x += alpha_{k-2} p_{k-2}, then += alpha_{k-1} p_{k-1}, on the
+// way; other iterations leave x alone, so x is read and written every other
+// iteration.
+template <bool VAR, bool AL, bool XU>
 LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, double *__restrict__ x, const double *__restrict__ r,
-                                   const double *__restrict__ pold, double *__restrict__ pnew,
-                                   double *__restrict__ q, const double *part_b, int nb_b, double *part_a,
-                                   PcgState *st, int k, double rtol) {
+                                   const double *__restrict__ pold, const double *__restrict__ pold2,
+                                   double *__restrict__ pnew, double *__restrict__ q, const double *part_b, int nb_b,
+                                   double *part_a, PcgState *st, int k, double rtol) {
     __shared__ double lds[kLdsDoubles];
     if (pcg_done_before_a(st, k)) return;
     double beta;
-    const double alpha = k > 1 ? st->alpha : 0.0;   // alpha_{k-1}
-    if (k > 1 && blockIdx.x == 0 && threadIdx.x == 0) st->x_pending = 0;
+    const double a1 = XU ? st->alpha[k & 1] : 0.0, a2 = XU ? st->alpha[(k - 1) & 1] : 0.0;
+    if (XU && blockIdx.x == 0 && threadIdx.x == 0) st->x_pending = 0;
     if (!pcg_a_begin(part_b, nb_b, st, k, rtol, lds, beta)) {
-        if (k > 1) x_update_all(g, x, pold, alpha);
+        x_update_at_stop<XU>(g, x, pold2, pold, st, k);
         return;
     }
     const bool first = k == 1;
@@ -196,14 +236,14 @@ LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, double *__restrict__ x, const double 
         R4 pc;
         const R4 qv = apply4g<VAR, AL>(pn, g, c, pc);
         store4<GUESS_F64>(pnew, c, toV(pc));
-        store4<GUESS_F64>(q, c, toV(qv));
+        store_q(q, c, toV(qv));
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(pc.v[e], qv.v[e], acc[0]);
-        if (!first) {
+        if constexpr (XU) {
             V4 xv = load4<GUESS_F64>(x, c);
-            const V4 pv = load4<GUESS_F64>(pold, c);
+            const V4 pv = load4<GUESS_F64>(pold2, c), pw = load4<GUESS_F64>(pold, c);
 #pragma unroll
-            for (int e = 0; e < 4; ++e) xv.v[e] = __builtin_fma(alpha, pv.v[e], xv.v[e]);
+            for (int e = 0; e < 4; ++e) xv.v[e] = __builtin_fma(a2, pw.v[e], __builtin_fma(a1, pv.v[e], xv.v[e]));
             store4<GUESS_F64>(x, c, xv);
         }
     }
@@ -211,7 +251,7 @@ LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, double *__restrict__ x, const double 
         const int64_t t = tail_start(g.n) + threadIdx.x;
         const double pt = pn(t);
         const double qt = apply_pt<VAR>(pn, g, t);
-        if (!first) x[t] = __builtin_fma(alpha, pold[t], x[t]);
+        if (XU) x[t] = __builtin_fma(a2, pold[t], __builtin_fma(a1, pold2[t], x[t]));
         pnew[t] = pt;
         q[t] = qt;
         acc[0] = __builtin_fma(pt, qt, acc[0]);
@@ -222,34 +262,46 @@ LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, double *__restrict__ x, const double 
 // ------------------------------------------------------------------ z-marching pcg_a
 // Same arithmetic as pcg_a_kernel in the traversal of march.h (constant
 // coefficient): p and q are bit-identical to the chunk form.
-template <bool VAR>
+template <bool VAR, bool XU>
 LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, double *__restrict__ x, const double *__restrict__ r,
-                                         const double *__restrict__ pold, double *__restrict__ pnew,
-                                         double *__restrict__ q, const double *part_b, int nb_b, double *part_a,
-                                         PcgState *st, int k, double rtol) {
+                                         const double *__restrict__ pold, const double *__restrict__ pold2,
+                                         double *__restrict__ pnew, double *__restrict__ q, const double *part_b,
+                                         int nb_b, double *part_a, PcgState *st, int k, double rtol) {
     __shared__ double lds[kLdsDoubles];
     if (pcg_done_before_a(st, k)) return;
     double beta;
-    const double alpha = k > 1 ? st->alpha : 0.0;   // alpha_{k-1}
-    if (k > 1 && blockIdx.x == 0 && threadIdx.x == 0) st->x_pending = 0;
+    const double a1 = XU ? st->alpha[k & 1] : 0.0, a2 = XU ? st->alpha[(k - 1) & 1] : 0.0;
+    if (XU && blockIdx.x == 0 && threadIdx.x == 0) st->x_pending = 0;
     if (!pcg_a_begin(part_b, nb_b, st, k, rtol, lds, beta)) {
-        if (k > 1) x_update_all(g, x, pold, alpha);
+        x_update_at_stop<XU>(g, x, pold2, pold, st, k);
         return;
     }
     const bool first = k == 1;
     const PNext<VAR> pn{r, pold, g.dinv, g.dinv_const, beta, first};
     double acc[1] = {0.0};
-    march_sweep<VAR>(g, m, pn, [&](int64_t c, int64_t e, const R2 &pa, const R2 &pb, const R4 &qv) {
-        if (!first) {
-            // deferred x += alpha_{k-1} p_{k-1} on this chunk
-            V4 xv = load4<GUESS_F64>(x, c);
-            const V4 ov = load4<GUESS_F64>(pold, c);
+    // x, p_{k-2} and p_{k-1} of the chunk, fetched one plane ahead for the deferred updates
+    struct XP {
+        V4 x, p1, p2;
+    };
+    auto pf = [&](int64_t c) {
+        XP v{};
+        if constexpr (XU) {
+            v.x = load4<GUESS_F64>(x, c);
+            v.p1 = load4<GUESS_F64>(pold2, c);
+            v.p2 = load4<GUESS_F64>(pold, c);
+        }
+        return v;
+    };
+    march_sweep_pf<VAR>(g, m, pn, pf, [&](int64_t c, int64_t e, const R2 &pa, const R2 &pb, const R4 &qv, const XP &xp) {
+        if constexpr (XU) {
+            // deferred x += alpha_{k-2} p_{k-2}, then += alpha_{k-1} p_{k-1}, on this chunk
+            V4 xv = xp.x;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) xv.v[i] = __builtin_fma(alpha, ov.v[i], xv.v[i]);
+            for (int i = 0; i < 4; ++i) xv.v[i] = __builtin_fma(a2, xp.p2.v[i], __builtin_fma(a1, xp.p1.v[i], xv.v[i]));
             store4<GUESS_F64>(x, c, xv);
         }
         store4<GUESS_F64>(pnew, c, V4{{pa.v[0], pa.v[1], pb.v[0], pb.v[1]}});
-        store4<GUESS_F64>(q, c, toV(qv));
+        store_q(q, c, toV(qv));
         acc[0] = __builtin_fma(pa.v[0], qv.v[0], acc[0]);
         acc[0] = __builtin_fma(pa.v[1], qv.v[1], acc[0]);
         acc[0] = __builtin_fma(pb.v[0], qv.v[2], acc[0]);
@@ -265,8 +317,12 @@ LG_REDUCE_KERNEL void pcg_init_march_kernel(Grid g, March m, const double *__res
                                             const double *__restrict__ x, double *__restrict__ r, double *part) {
     __shared__ double lds[kLdsDoubles];
     double acc[3] = {0.0, 0.0, 0.0};
-    march_sweep<VAR>(g, m, VecU{x}, [&](int64_t c, int64_t, const R2 &, const R2 &, const R4 &ax) {
-        const V4 bv = load4<GUESS_F64>(b, c), dv = dinv4<VAR>(g, c);
+    struct BD {
+        V4 b, d;
+    };
+    auto pf = [&](int64_t c) { return BD{load4<GUESS_F64>(b, c), dinv4<VAR>(g, c)}; };
+    march_sweep_pf<VAR>(g, m, VecU{x}, pf, [&](int64_t c, int64_t, const R2 &, const R2 &, const R4 &ax, const BD &bd) {
+        const V4 &bv = bd.b, &dv = bd.d;
         V4 rv;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -297,14 +353,15 @@ LG_REDUCE_KERNEL void pcg_b_kernel(Grid g, double *__restrict__ r, const double 
     }
     const double alpha = st->rho[k & 1] / pq;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->alpha = alpha;
+        st->alpha[k & 1] = alpha;
+        st->x_last = k;
         st->x_pending = 1;
     }
     double acc[3] = {0.0, 0.0, 0.0};
     const int64_t nc = nchunks(g.n), stride = (int64_t)gridDim.x * kBlock;
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
         V4 rv = load4<GUESS_F64>(r, c);
-        const V4 qv = load4<GUESS_F64>(q, c), dv = dinv4<VAR>(g, c);
+        const V4 qv = load_q(q, c), dv = dinv4<VAR>(g, c);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             rv.v[e] = __builtin_fma(-alpha, qv.v[e], rv.v[e]);
@@ -343,25 +400,34 @@ int launch_pcg_init(const Grid &g, const double *b, const double *x, double *r, 
     return GUESS_OK;
 }
 
-template <bool VAR, bool AL>
-static void pcg_iter_v(const Grid &g, double *x, double *r, double *const p[2], double *q, double *part_a,
+template <bool VAR, bool AL, bool XU>
+static void pcg_iter_x(const Grid &g, double *x, double *r, double *const p[3], double *q, double *part_a,
                        double *part_b, PcgState *st, int k, double rtol, hipStream_t s) {
     const int gr = pcg_grid(g);
-    double *pnew = p[k & 1];
-    const double *pold = p[(k - 1) & 1];
+    double *pnew = p[k % 3];
+    const double *pold = p[(k - 1) % 3], *pold2 = p[(k + 1) % 3];    // p_{k-1}, p_{k-2}
     int ga = gr;
     if (AL && march_ok(g) && march_enabled()) {
-        const int wgs = resident_wgs<pcg_a_march_kernel<VAR>>();
+        const int wgs = resident_wgs<pcg_a_march_kernel<VAR, XU>>();
         const March m = make_march(g, wgs);
         ga = march_grid(m);
-        pcg_a_march_kernel<VAR><<<ga, kBlock, 0, s>>>(g, m, x, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
+        pcg_a_march_kernel<VAR, XU><<<ga, kBlock, 0, s>>>(g, m, x, r, pold, pold2, pnew, q, part_b, gr, part_a, st,
+                                                          k, rtol);
     } else {
-        pcg_a_kernel<VAR, AL><<<gr, kBlock, 0, s>>>(g, x, r, pold, pnew, q, part_b, gr, part_a, st, k, rtol);
+        pcg_a_kernel<VAR, AL, XU><<<gr, kBlock, 0, s>>>(g, x, r, pold, pold2, pnew, q, part_b, gr, part_a, st, k,
+                                                        rtol);
     }
     pcg_b_kernel<VAR><<<gr, kBlock, 0, s>>>(g, r, q, part_a, ga, part_b, st, k);
 }
 
-int launch_pcg_iter(const Grid &g, double *x, double *r, double *const p[2], double *q, double *part_a,
+template <bool VAR, bool AL>
+static void pcg_iter_v(const Grid &g, double *x, double *r, double *const p[3], double *q, double *part_a,
+                       double *part_b, PcgState *st, int k, double rtol, hipStream_t s) {
+    if ((k & 1) && k >= 3) pcg_iter_x<VAR, AL, true>(g, x, r, p, q, part_a, part_b, st, k, rtol, s);
+    else pcg_iter_x<VAR, AL, false>(g, x, r, p, q, part_a, part_b, st, k, rtol, s);
+}
+
+int launch_pcg_iter(const Grid &g, double *x, double *r, double *const p[3], double *q, double *part_a,
                     double *part_b, PcgState *st, int k, double rtol, hipStream_t s) {
     if (g.kx) {
         if (g.aligned) pcg_iter_v<true, true>(g, x, r, p, q, part_a, part_b, st, k, rtol, s);
@@ -402,14 +468,20 @@ int launch_pcg_check(const Grid &g, const double *part_b, PcgState *st, int k, d
     return GUESS_OK;
 }
 
-// The x update of the last completed iteration when no later pcg_a applied it.
-__global__ __launch_bounds__(kBlock) void pcg_finish_kernel(Grid g, double *x, const double *p, PcgState *st) {
+// The x updates that no later pcg_a applied: those of the last completed
+// iteration L and, for even L, of L-1 (odd iterations apply the two before them).
+__global__ __launch_bounds__(kBlock) void pcg_finish_kernel(Grid g, double *x, const double *p0, const double *p1,
+                                                            const double *p2, PcgState *st) {
     if (!st->x_pending) return;
-    x_update_all(g, x, p, st->alpha);
+    const int L = st->x_last;
+    const double *p[3] = {p0, p1, p2};
+    if (L % 2 == 0) x_update_all<true>(g, x, p[(L - 1) % 3], st->alpha[(L - 1) & 1], p[L % 3], st->alpha[L & 1]);
+    else x_update_all<false>(g, x, p[L % 3], st->alpha[L & 1], nullptr, 0.0);
 }
 
-int launch_pcg_finish(const Grid &g, double *x, const double *p, PcgState *st, hipStream_t s) {
-    pcg_finish_kernel<<<stream_grid(nchunks(g.n) > 0 ? nchunks(g.n) : 1, grid_cap()), kBlock, 0, s>>>(g, x, p, st);
+int launch_pcg_finish(const Grid &g, double *x, double *const p[3], PcgState *st, hipStream_t s) {
+    pcg_finish_kernel<<<stream_grid(nchunks(g.n) > 0 ? nchunks(g.n) : 1, grid_cap()), kBlock, 0, s>>>(
+        g, x, p[0], p[1], p[2], st);
     return GUESS_OK;
 }
 

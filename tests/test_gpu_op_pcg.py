@@ -243,6 +243,46 @@ def test_pcg_edge_cases(lib):
         L.guess_op_destroy(A)
 
 
+@pytest.mark.parametrize("n", [12, 32])
+def test_pcg_deferred_updates_every_count(lib, n):
+    """x is updated every other iteration (odd iterations apply the two updates before them), so
+    what a solve leaves pending depends on the parity of its last iteration.  For K = 1 .. 7
+    iterations: the solve capped at K (ending with the check and finishing kernels) equals the
+    oracle's K-th iterate to 1e-12, and the solve that stops inside iteration K + 1's stencil
+    kernel (its stop test passes on r_K) equals the capped one bit for bit.  12^3: chunk form
+    with a ragged tail; 32^3: the z-marching form."""
+    import torch
+
+    L = lib
+    N = n ** 3
+    A = make_op(L, n)
+    Aop = op.Operator(n)
+    b = synth.random_vectors(91, 1, N)[0]
+    capped, rrs = {}, {}
+    try:
+        for K in range(1, 8):
+            announce(f"pcg n={n} capped at {K} iterations")
+            x1 = torch.zeros(N, dtype=torch.float64, device="cuda")
+            st, it, rrs[K] = L.pcg_solve(A, dev(b), x1, 1e-30, K)
+            assert st == L.ENOTCONV and it == K
+            capped[K] = host(x1).copy()
+            xo, ito, _, _ = oracle_pcg(Aop, b, np.zeros_like(b), 1.0 / Aop.diag(), 1e-30, K)
+            assert ito == K
+            assert rel_inf(capped[K], xo) <= 1e-12, (K, rel_inf(capped[K], xo))
+        # a tolerance just above the relative residual after K iterations stops the solve in
+        # iteration K + 1 when no earlier residual was as small
+        stops = [K for K in rrs if all(rrs[K] * (1.0 + 1e-9) < rrs[j] for j in range(1, K))]
+        assert {K % 2 for K in stops} == {0, 1}, rrs
+        for K in stops:
+            announce(f"pcg n={n} stopping after {K} iterations")
+            x2 = torch.zeros(N, dtype=torch.float64, device="cuda")
+            st2, it2, _ = L.pcg_solve(A, dev(b), x2, rrs[K] * (1.0 + 1e-9), 100)
+            assert st2 == L.OK and it2 == K, (K, it2)
+            assert np.array_equal(host(x2), capped[K]), K
+    finally:
+        L.guess_op_destroy(A)
+
+
 def test_plane_wave_rhs_kernel(lib):
     import torch
 
