@@ -170,6 +170,10 @@ def parse():
     p.add_argument("--calibrate-copy", action="store_true",
                    help="only run the plain copy kernel (1 GiB -> 1 GiB, 5 launches); used to scale "
                         "the FETCH_SIZE / WRITE_SIZE counters of a profiled run")
+    p.add_argument("--traffic-summary", nargs=4, metavar=("FETCH", "WRITE", "FETCH_COPY", "WRITE_COPY"),
+                   help="no GPU: write profiles/hbm_traffic.txt from four rocprofv3 --pmc output folders "
+                        "(FETCH_SIZE and WRITE_SIZE of a profiled bench run whose JSON line is FETCH/bench.json, "
+                        "and of --calibrate-copy)")
     return p.parse_args()
 
 
@@ -234,6 +238,109 @@ def hbm_traffic(kernel):
     v = rec.get(f"{kernel}.bytes_per_launch")
     a = rec.get(f"{kernel}.algorithmic_bytes_per_launch")
     return (float(v), float(a)) if v and a else None
+
+
+# Kernel-name patterns of the counter CSVs -> bench kernel names; PCG's kernels with their
+# algorithmic bytes per unknown (constant coefficient).
+TRAFFIC_GUESS = [("extrap_form", "extrap_form_kernel"), ("ring_store", "ring_store_kernel"),
+                 ("proj_dots", "proj_dots_kernel"), ("proj_combine", "proj_combine_kernel"),
+                 ("proj_apply", "proj_apply_"), ("proj_reorth", "proj_reorth_kernel"),
+                 ("proj_gs_write", "proj_gs_write_kernel")]
+TRAFFIC_PCG = [("pcg_a_xupdate", "pcg_a_march_kernel<false, true>", 32, 24),
+               ("pcg_a", "pcg_a_march_kernel<false, false>", 16, 16),
+               ("pcg_b", "pcg_b_kernel<false>", 16, 8)]
+TRAFFIC_SOURCES = ["paper_2009_10863_amd/_build.py", "paper_2009_10863_amd/csrc/common.h",
+                   "paper_2009_10863_amd/csrc/extrap.hip", "paper_2009_10863_amd/csrc/launch.h",
+                   "paper_2009_10863_amd/csrc/march.h", "paper_2009_10863_amd/csrc/pcg.hip",
+                   "paper_2009_10863_amd/csrc/proj_impl.h", "paper_2009_10863_amd/csrc/proj_inst.hip",
+                   "paper_2009_10863_amd/csrc/stencil.h"]
+
+
+def traffic_summary(args):
+    """profiles/hbm_traffic.txt from the counter runs: per kernel the mean FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads for the copy
+    kernel moving 1 GiB -> 1 GiB, beside the algorithmic bytes per launch of the same run (the
+    bench JSON line of the profiled command: every step timed, so its launches are the
+    dispatches counted)."""
+    import csv
+    import glob
+    import hashlib
+
+    def counter(folder, name, pattern):
+        # dispatches that moved data: a launch that returns at once (a projection call on an
+        # empty history, PCG kernels of a batch after convergence) reads a few KiB
+        vals = []
+        for f in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+            for row in csv.DictReader(open(f)):
+                if row["Counter_Name"] == name and pattern in row["Kernel_Name"]:
+                    vals.append(float(row["Counter_Value"]) * 1024.0)
+        if not vals:
+            return None, 0
+        big = sorted(vals)[len(vals) // 2] * 0.01
+        vals = [v for v in vals if v >= big]
+        return sum(vals), len(vals)
+
+    fdir, wdir, fcopy, wcopy = args.traffic_summary
+    gib = float(1 << 30)
+    fc, nfc = counter(fcopy, "FETCH_SIZE", "copy_kernel")
+    wc, nwc = counter(wcopy, "WRITE_SIZE", "copy_kernel")
+    fscale, wscale = gib / (fc / nfc), gib / (wc / nwc)
+    run = json.loads(open(os.path.join(fdir, "bench.json")).read().strip().splitlines()[-1])
+    N = run["config"]["n"] ** 3
+    h = hashlib.sha256()
+    for f in sorted(TRAFFIC_SOURCES):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    rows = []
+    entries = [(k, pat, run["kernels"][k]["bytes_per_launch"], run["kernels"][k]["launches"], None, None)
+               for k, pat in TRAFFIC_GUESS if k in run["kernels"]]
+    entries += [(k, pat, (r + w) * N, None, r * N, w * N) for k, pat, r, w in TRAFFIC_PCG]
+    for k, pat, alg, launches, ar, aw in entries:
+        fb, nf = counter(fdir, "FETCH_SIZE", pat)
+        wb, nw = counter(wdir, "WRITE_SIZE", pat)
+        if fb is None or wb is None:
+            continue
+        # per launch: the run's totals over its launches that moved data (the bench's own count
+        # for the guess kernels, whose launch on an empty history may only write)
+        nl = launches if launches is not None else nf
+        rd, wr = fb * fscale / nl, wb * wscale / nl
+        rows.append(f"{k}.bytes_per_launch = {rd + wr:.0f}")
+        rows.append(f"{k}.read_bytes_per_launch = {rd:.0f}")
+        rows.append(f"{k}.write_bytes_per_launch = {wr:.0f}")
+        rows.append(f"{k}.algorithmic_bytes_per_launch = {alg:.0f}")
+        if ar is not None:
+            rows.append(f"{k}.algorithmic_read_bytes_per_launch = {ar:.0f}")
+            rows.append(f"{k}.algorithmic_write_bytes_per_launch = {aw:.0f}")
+        rows.append(f"{k}.ratio = {(rd + wr) / alg:.4f}")
+        rows.append(f"{k}.dispatches = {nf} fetch, {nw} write" +
+                    (f" (bench launches {launches})" if launches is not None else ""))
+    cmd = run.get("command", "")
+    head = [
+        f"# HBM bytes per launch, {run['config']['workload']}: FETCH_SIZE and WRITE_SIZE (KiB per dispatch,",
+        "# one rocprofv3 --pmc run each), scaled by what the same counters read for the plain copy kernel",
+        f"# moving 1 GiB -> 1 GiB (FETCH_SIZE x {fscale:.4f}, WRITE_SIZE x {wscale:.4f}); algorithmic bytes",
+        "# of the guess kernels from the profiled run's own JSON line, of PCG's kernels per unknown",
+        "# (pcg_a_xupdate: the odd iterations that also update x, 56 B; pcg_a: 32 B; pcg_b: 24 B).",
+        "# Dispatches that return at once (reading < 1 % of the kernel's median) are left out.",
+        "# Valid while the sources below hash to sha256.  Commands (from /tmp, TMPDIR=/tmp):",
+        "#   rocprofv3 --pmc FETCH_SIZE -f csv --kernel-include-regex \"extrap_form|ring_store|proj_|copy_kernel|pcg_\" "
+        "-d gpurun_out/prof_FETCH_SIZE -o bench -- python3 bench.py --steps 15 --warmup 0 --no-cpu-baseline "
+        "--no-small-sequence --precision-steps 0 > gpurun_out/prof_FETCH_SIZE/bench.json",
+        "#   (the same with WRITE_SIZE and gpurun_out/prof_WRITE_SIZE)",
+        "#   rocprofv3 --pmc FETCH_SIZE -f csv --kernel-include-regex copy_kernel -d gpurun_out/prof_FETCH_SIZE_copy "
+        "-o copy -- python3 bench.py --calibrate-copy",
+        "#   (the same with WRITE_SIZE and gpurun_out/prof_WRITE_SIZE_copy)",
+        "#   python3 bench.py --traffic-summary gpurun_out/prof_FETCH_SIZE gpurun_out/prof_WRITE_SIZE "
+        "gpurun_out/prof_FETCH_SIZE_copy gpurun_out/prof_WRITE_SIZE_copy",
+        f"sources = {','.join(sorted(TRAFFIC_SOURCES))}",
+        f"sha256 = {h.hexdigest()}",
+        f"fetch_scale = {fscale:.6f}",
+        f"write_scale = {wscale:.6f}",
+    ]
+    del cmd
+    out = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    with open(out, "w") as f:
+        f.write("\n".join(head + rows) + "\n")
+    print(f"wrote {out}")
 
 
 def cpu_baseline(args, s_bytes):
@@ -662,6 +769,9 @@ def adjoint_run(args, L):
 
 def main():
     args = parse()
+    if args.traffic_summary:
+        traffic_summary(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout "
               "is a design note, not a measured path.", file=sys.stderr)
