@@ -59,21 +59,6 @@ __device__ __forceinline__ V4 dinv4(const Grid &g, int64_t c) {
     else return V4{{g.dinv_const, g.dinv_const, g.dinv_const, g.dinv_const}};
 }
 
-// q = A p is written by pcg_a and read once by the pcg_b that follows; unlike the
-// other vectors it goes through the caches with ordinary stores and loads (a
-// PCG iteration at 256^3 measured 1.8 % faster than with non-temporal ones,
-// which stay the rule for x, r and p: there cached accesses were slower).
-__device__ __forceinline__ void store_q(double *q, int64_t c, const V4 &v) {
-    const int64_t e = chunk_elem(c);
-    *reinterpret_cast<d2 *>(q + e) = d2{v.v[0], v.v[1]};
-    *reinterpret_cast<d2 *>(q + e + 128) = d2{v.v[2], v.v[3]};
-}
-__device__ __forceinline__ V4 load_q(const double *q, int64_t c) {
-    const int64_t e = chunk_elem(c);
-    const d2 a = *reinterpret_cast<const d2 *>(q + e), b = *reinterpret_cast<const d2 *>(q + e + 128);
-    return V4{{a.x, a.y, b.x, b.y}};
-}
-
 // The next search direction as a stencil operand: p = D^{-1} r + beta p_old
 // (first iteration: p = D^{-1} r), evaluated wherever the stencil reads it.
 template <bool VAR>
@@ -236,7 +221,7 @@ LG_REDUCE_KERNEL void pcg_a_kernel(Grid g, double *__restrict__ x, const double 
         R4 pc;
         const R4 qv = apply4g<VAR, AL>(pn, g, c, pc);
         store4<GUESS_F64>(pnew, c, toV(pc));
-        store_q(q, c, toV(qv));
+        store4<GUESS_F64>(q, c, toV(qv));
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[0] = __builtin_fma(pc.v[e], qv.v[e], acc[0]);
         if constexpr (XU) {
@@ -301,7 +286,7 @@ LG_REDUCE_KERNEL void pcg_a_march_kernel(Grid g, March m, double *__restrict__ x
             store4<GUESS_F64>(x, c, xv);
         }
         store4<GUESS_F64>(pnew, c, V4{{pa.v[0], pa.v[1], pb.v[0], pb.v[1]}});
-        store_q(q, c, toV(qv));
+        store4<GUESS_F64>(q, c, toV(qv));
         acc[0] = __builtin_fma(pa.v[0], qv.v[0], acc[0]);
         acc[0] = __builtin_fma(pa.v[1], qv.v[1], acc[0]);
         acc[0] = __builtin_fma(pb.v[0], qv.v[2], acc[0]);
@@ -361,7 +346,7 @@ LG_REDUCE_KERNEL void pcg_b_kernel(Grid g, double *__restrict__ r, const double 
     const int64_t nc = nchunks(g.n), stride = (int64_t)gridDim.x * kBlock;
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < nc; c += stride) {
         V4 rv = load4<GUESS_F64>(r, c);
-        const V4 qv = load_q(q, c), dv = dinv4<VAR>(g, c);
+        const V4 qv = load4<GUESS_F64>(q, c), dv = dinv4<VAR>(g, c);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             rv.v[e] = __builtin_fma(-alpha, qv.v[e], rv.v[e]);
