@@ -25,6 +25,7 @@ constexpr int kBlock = 256;          // threads per workgroup (4 wave64s)
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxPartialBlocks = 2048;
 constexpr int kMaxDots = 2 * GUESS_MAX_M + 4;
+constexpr int kPartialDoubles = kMaxPartialBlocks * kMaxDots;   // capacity of a partial-row buffer
 
 // ------------------------------------------------------------------ storage types
 // DT: GUESS_F64 / F32 / F16 / BF16.  Stored element type and conversions.
@@ -245,7 +246,20 @@ __device__ __forceinline__ void final_sums(const double *part, int nb, double (&
     double v[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) v[j] = 0.0;
-    for (int r = threadIdx.x; r < nb; r += kBlock) {
+    int r = threadIdx.x;
+    // four rows in flight per thread, combined in row order
+    for (; r + 3 * kBlock < nb; r += 4 * kBlock) {
+        double x[4][ND];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < ND; ++j) x[q][j] = __builtin_nontemporal_load(part + (int64_t)(r + q * kBlock) * ND + j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < ND; ++j) v[j] = j < NS ? v[j] + x[q][j] : nanmax(v[j], x[q][j]);
+    }
+    for (; r < nb; r += kBlock) {
         const double *row = part + (int64_t)r * ND;
 #pragma unroll
         for (int j = 0; j < ND; ++j) {

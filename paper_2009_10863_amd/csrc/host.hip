@@ -84,6 +84,14 @@ int grid_cap() {
     return v;
 }
 
+int write_blocks() {
+    static const int v = [] {
+        int x = env_int("LIBGUESS_WRITE_BLOCKS", 0);
+        return x < 0 ? 0 : x;
+    }();
+    return v;
+}
+
 int reduce_blocks() {
     static const int v = [] {
         int x = env_int("LIBGUESS_REDUCE_BLOCKS", 1024);

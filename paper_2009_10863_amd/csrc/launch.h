@@ -165,6 +165,8 @@ int launch_gaussian_rhs(int n, const double *center, double sigma, double amp, d
 
 // grid-size knob for the streaming kernels (LIBGUESS_GRID_CAP, default below)
 int grid_cap();
+// workgroups of the Gram-Schmidt write pass (LIBGUESS_WRITE_BLOCKS; 0: one chunk per thread)
+int write_blocks();
 int reduce_blocks();
 bool march_enabled();
 

@@ -911,8 +911,15 @@ void proj_update_dt(const ProjBufs &p, const Grid *g, const double *x, const dou
     const double *w = Ax ? Ax : a.w;
     klaunch(ev, 2, proj_reorth_kernel<DT, VF>, gr, kBlock, s, a, x, w);
     klaunch(ev, 3, proj_fin_kernel<FIN_REORTH, VF, DT>, 1, kBlock, s, a, gr);
-    klaunch(ev, 4, proj_gs_write_kernel<DT, VF>, gr, kBlock, s, a, x, w);
-    klaunch(ev, 5, proj_fin_kernel<FIN_GS, VF, DT>, 1, kBlock, s, a, gr);
+    // The write pass stores two columns: one chunk per thread, so that no loop iteration waits
+    // on the stores of the one before (partial rows: at most 2 per workgroup, M + 1 for an FP16
+    // rolling drop, within the buffer's capacity).
+    const int ndw = (scaled_store<DT>() && (VF & VF_QR) != 0) ? a.M + 1 : 2;
+    int wcap = kPartialDoubles / ndw;
+    if (write_blocks() > 0 && write_blocks() < wcap) wcap = write_blocks();
+    const int gw = stream_grid(nchunks(a.N), wcap);
+    klaunch(ev, 4, proj_gs_write_kernel<DT, VF>, gw, kBlock, s, a, x, w);
+    klaunch(ev, 5, proj_fin_kernel<FIN_GS, VF, DT>, 1, kBlock, s, a, gw);
 }
 
 }  // namespace lg
