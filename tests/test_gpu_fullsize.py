@@ -202,31 +202,34 @@ def test_projection_variants_256_m8_properties(lib, method):
 
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
-def test_proj_256_lowprec_replay(lib, dtype):
+@pytest.mark.parametrize("method,dtype", [("proj", "f32"), ("proj", "f16"), ("proj", "bf16"), ("projqr", "f16")])
+def test_proj_256_lowprec_replay(lib, method, dtype):
     """Reduced-precision PROJ(8) at the benchmark's size against the oracle: seven random
     solutions of growing magnitude and random right-hand sides.  After every update the newest
     stored column equals the oracle's bit for bit, except where the two FP64 remainders round
     to different neighbours of the format (a difference within one unit of the format plus
     64 u times the raw pair in stored units; at most 1e-6 of the values); the oracle then takes
     the library's stored history, so every guess is compared from identical states and held
-    to 1e-12 relative -- the per-format guess error against the oracle at 256^3."""
+    to 1e-12 relative -- the per-format guess error against the oracle at 256^3.  The FP16
+    rolling window runs ten steps, so that its last two updates drop the oldest column (the
+    write pass then reduces M + 1 values per workgroup)."""
     import torch
 
     from proj_replay import resync
 
-    announce(f"proj 256^3 M=8 {dtype} random replay")
+    announce(f"{method} 256^3 M=8 {dtype} random replay")
     L = lib
-    M, T = 8, 7
+    M, T = 8, (10 if method == "projqr" else 7)
+    meth, _ = L.parse_method(method)
     A = L.guess_op_create(n, n, n, float((n + 1) ** 2), 10.0, None)
-    g = L.guess_create_ex(N, M, L.PROJ, 0, L.DTYPES[dtype], 1e-6, A)
+    g = L.guess_create_ex(N, M, meth, 0, L.DTYPES[dtype], 1e-6, A)
     Aop = op.Operator(n)
-    ref = Projection(M, Aop, 1e-6, dtype, "classic", "A")
+    ref = Projection(M, Aop, 1e-6, dtype, "qr" if method == "projqr" else "classic", "A")
     x0 = torch.empty(N, dtype=torch.float64, device="cuda")
     buf = torch.empty(N, dtype=torch.float64, device="cuda")
     u = lowprec.UNIT_ROUNDOFF[dtype]
     rng = np.random.default_rng(18)
-    flips, worst = 0, 0.0
+    flips, worst, compared, drops = 0, 0.0, 0, 0
     try:
         for s in range(T):
             b = rng.standard_normal(N)
@@ -247,23 +250,30 @@ def test_proj_256_lowprec_replay(lib, dtype):
                 xs = host(buf).copy()
                 L.guess_history_raw(g, 1, j, buf)
                 raw.append((xs, host(buf).copy(), sx))
-            xs, bs, sc = raw[-1]
-            j = ref.d - 1
-            assert abs(sc - ref.sig[j]) <= 1e-13 * ref.sig[j]
             xmax = max(float(np.max(np.abs(x))), float(np.max(np.abs(Aop(x)))))
-            for got, wcol in ((xs, ref.S[j]), (bs, ref.T[j])):
-                diff = got.view(np.uint64) != wcol.view(np.uint64)
-                if diff.any():
-                    mag = max(float(np.max(np.abs(wcol))), xmax / (sc * info["nu"]))
-                    dv = np.abs(got[diff] - wcol[diff])
-                    assert np.all(dv <= 2 * u * np.abs(wcol[diff]) + 64 * 2.0 ** -53 * mag), (s, int(diff.sum()))
-                    flips += int(diff.sum())
-            if dtype == "f16":
-                assert np.max(np.abs(xs)) <= 2 ** 15 and np.max(np.abs(bs)) <= 2 ** 15
+            # the newest column; after a rolling drop every column (all were rotated and stored again)
+            cols = range(ref.d) if info["drops"] > drops else [ref.d - 1]
+            drops = info["drops"]
+            cmax = max(max(float(np.max(np.abs(S))), float(np.max(np.abs(T)))) for S, T in zip(ref.S, ref.T))
+            for j in cols:
+                xs, bs, sc = raw[j]
+                assert abs(sc - ref.sig[j]) <= 1e-13 * ref.sig[j], (s, j)
+                for got, wcol in ((xs, ref.S[j]), (bs, ref.T[j])):
+                    diff = got.view(np.uint64) != wcol.view(np.uint64)
+                    if diff.any():
+                        mag = 2 * cmax if j < ref.d - 1 else max(cmax, xmax / (sc * info["nu"]))
+                        dv = np.abs(got[diff] - wcol[diff])
+                        assert np.all(dv <= 2 * u * np.abs(wcol[diff]) + 64 * 2.0 ** -53 * mag), (s, j, int(diff.sum()))
+                        flips += int(diff.sum())
+                if dtype == "f16":
+                    assert np.max(np.abs(xs)) <= 2 ** 15 and np.max(np.abs(bs)) <= 2 ** 15
+                compared += 2 * N
             resync(L, g, ref, raw)
     finally:
         L.guess_destroy(g)
         L.guess_op_destroy(A)
-    print(f"[replay] proj {dtype} 256^3: {T} steps, {flips} of {T * 2 * N} stored values differ, "
-          f"largest guess error {worst:.2e}", flush=True)
-    assert flips <= 1e-6 * T * 2 * N
+    print(f"[replay] {method} {dtype} 256^3: {T} steps, {drops} drops, {flips} of {compared} stored values "
+          f"differ, largest guess error {worst:.2e}", flush=True)
+    assert flips <= 1e-6 * compared
+    if method == "projqr":
+        assert drops == T - M
