@@ -420,9 +420,13 @@ int guess_copy_kernel(void *dst, const void *src, size_t bytes, void *stream);
  *   GUESS_ROOF_READ:  reads `bytes` of src (multiple of 16 counted) and
  *                     writes one FP64 partial sum per workgroup into dst,
  *                     which must hold 2048 doubles (16 KiB);
- *   GUESS_ROOF_WRITE: writes `bytes` of dst (src unused, may be NULL).
+ *   GUESS_ROOF_WRITE: writes `bytes` of dst (src unused, may be NULL);
+ *   GUESS_ROOF_READ_STREAMS: as GUESS_ROOF_READ, with src read as 16 equal
+ *                     segments streamed side by side (the pattern of a pass
+ *                     over 16 vectors); bytes / 16 rounded down to a
+ *                     multiple of 16 elements are read.
  * Device pointers, 16-byte aligned; EINVAL otherwise or for another mode. */
-enum { GUESS_ROOF_COPY = 0, GUESS_ROOF_READ = 1, GUESS_ROOF_WRITE = 2 };
+enum { GUESS_ROOF_COPY = 0, GUESS_ROOF_READ = 1, GUESS_ROOF_WRITE = 2, GUESS_ROOF_READ_STREAMS = 3 };
 int guess_roof_kernel(int mode, void *dst, const void *src, size_t bytes, void *stream);
 
 #ifdef __cplusplus

@@ -1278,9 +1278,11 @@ extern "C" int guess_roof_kernel(int mode, void *dst, const void *src, size_t by
     switch (mode) {
         case GUESS_ROOF_COPY: return guess_copy_kernel(dst, src, bytes, stream);
         case GUESS_ROOF_READ:
+        case GUESS_ROOF_READ_STREAMS:
             if (!dst || !src) return fail(GUESS_EINVAL, "guess_roof_kernel: NULL argument");
             if (!aligned16(src) || !aligned16(dst)) return fail(GUESS_EINVAL, "guess_roof_kernel: need 16-byte alignment");
-            LG_TRY(lg::launch_read(src, bytes, (double *)dst, s));
+            if (mode == GUESS_ROOF_READ) LG_TRY(lg::launch_read(src, bytes, (double *)dst, s));
+            else LG_TRY(lg::launch_read_streams(src, bytes, (double *)dst, s));
             return check_launch("guess_roof_kernel");
         case GUESS_ROOF_WRITE:
             if (!dst) return fail(GUESS_EINVAL, "guess_roof_kernel: NULL argument");

@@ -157,6 +157,7 @@ int launch_multidot(int64_t N, int K, const double *V, const double *y, double *
 int launch_combine(int64_t N, int K, const double *V, const double *c, double *y, hipStream_t s);
 int launch_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 int launch_read(const void *src, size_t bytes, double *out, hipStream_t s);
+int launch_read_streams(const void *src, size_t bytes, double *out, hipStream_t s);
 int launch_write(void *dst, size_t bytes, hipStream_t s);
 int launch_plane_wave_rhs(int n, int K, const double *tabx, const double *taby,
                           const double *tabz, const double *amp, double *b, hipStream_t s);

@@ -128,6 +128,30 @@ __global__ __launch_bounds__(kBlock) void read_kernel(const d2 *__restrict__ src
     block_partials<1>(acc, out, lds);
 }
 
+// The same read traffic as K separate vectors: `src` taken as K equal
+// segments, each thread reading element t of every segment per step of a
+// grid-stride loop (the access pattern of a pass that streams K vectors).
+template <int K>
+__global__ __launch_bounds__(kBlock) void read_streams_kernel(const d2 *__restrict__ src, int64_t seg,
+                                                              double *__restrict__ out) {
+    __shared__ double lds[kLdsDoubles];
+    const int64_t S = (int64_t)gridDim.x * kBlock;
+    double acc[1] = {0.0};
+    double part[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) part[k] = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < seg; t += S) {
+        d2 v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = __builtin_nontemporal_load(src + k * seg + t);
+#pragma unroll
+        for (int k = 0; k < K; ++k) part[k] += v[k].x + v[k].y;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[0] += part[k];
+    block_partials<1>(acc, out, lds);
+}
+
 template <int U>
 __global__ __launch_bounds__(kBlock) void write_kernel(d2 *__restrict__ dst, int64_t n16, double v) {
     const int64_t S = (int64_t)gridDim.x * kBlock;
@@ -167,6 +191,20 @@ int launch_read(const void *src, size_t bytes, double *out, hipStream_t s) {
         case 8: read_kernel<8><<<grid, kBlock, 0, s>>>(p, n16, out); break;
         default: read_kernel<1><<<grid, kBlock, 0, s>>>(p, n16, out); break;
     }
+    return GUESS_OK;
+}
+
+// Sixteen streams (the second Gram-Schmidt pass at d = 7 reads 2d + 2) on the
+// reduction grid of the guess kernels.
+constexpr int kRoofStreams = 16;
+
+int launch_read_streams(const void *src, size_t bytes, double *out, hipStream_t s) {
+    const int64_t seg = (int64_t)(bytes / 16) / kRoofStreams;
+    if (seg <= 0) return GUESS_OK;
+    int grid = roof_env("LIBGUESS_ROOF_GRID", reduce_blocks());
+    grid = grid < 1 ? 1 : (grid > kMaxPartialBlocks ? kMaxPartialBlocks : grid);
+    grid = stream_grid(seg, grid);
+    read_streams_kernel<kRoofStreams><<<grid, kBlock, 0, s>>>((const d2 *)src, seg, out);
     return GUESS_OK;
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("LIBGUESS_SO") or os.path.join(_HERE, "_lib", "libgues
 ZERO, LAST, EXTRAP, PROJ, SPEXTRAP, PROJ_QR, PROJ_RAW, PROJ_RAW_QR = 0, 1, 2, 3, 4, 5, 6, 7
 INNER_A, INNER_L2 = 0, 1
 F64, F32, F16, BF16 = 0, 1, 2, 3
-ROOF_COPY, ROOF_READ, ROOF_WRITE = 0, 1, 2
+ROOF_COPY, ROOF_READ, ROOF_WRITE, ROOF_READ_STREAMS = 0, 1, 2, 3
 OK, EINVAL, ENOMEM, EHIP, ENOTCONV, EBREAKDOWN, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 STOP_RHS, STOP_INITRESID = 0, 1
 MAX_M = 16
@@ -372,7 +372,7 @@ def guess_copy_kernel(dst, src, nbytes, stream=None) -> None:
 def guess_roof_kernel(mode, dst, src, nbytes, stream=None) -> None:
     """Copy / read-only / write-only bandwidth reference (the read mode writes 2048 partial
     sums into dst)."""
-    need_dst = 2048 * 8 if mode == ROOF_READ else nbytes
+    need_dst = 2048 * 8 if mode in (ROOF_READ, ROOF_READ_STREAMS) else nbytes
     _check(_lib.guess_roof_kernel(mode, addr(dst, need_dst, "dst", f64=False),
                                   addr(src, nbytes if mode != ROOF_WRITE else None, "src", f64=False),
                                   nbytes, stream))

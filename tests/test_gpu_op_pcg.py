@@ -324,3 +324,33 @@ def test_vector_kernels(lib):
     dst = torch.zeros_like(src)
     L.guess_copy_kernel(dst, src, 12345 * 8)
     assert np.array_equal(host(dst), np.arange(12345, dtype=np.float64))
+
+
+def test_roof_kernels(lib):
+    """The bandwidth references read and write what they claim: the read kernels' partial rows
+    sum to the sum of the bytes they read (one stream; 16 segments side by side, of which
+    bytes / 16 rounded down to a multiple of 16 elements count), the write kernel fills dst,
+    the copy copies."""
+    import torch
+
+    announce("roof kernels")
+    L = lib
+    n = 1 << 16                       # doubles; 2^15 16-byte elements
+    v = np.arange(n, dtype=np.float64) % 97.0
+    src = dev(v)
+    part = torch.zeros(2048, dtype=torch.float64, device="cuda")
+    L.guess_roof_kernel(L.ROOF_READ, part, src, n * 8)
+    torch.cuda.synchronize()
+    assert float(part.sum()) == float(v.sum())
+    part.zero_()
+    nbytes = n * 8 - 48                # 2^15 - 3 elements: 16 segments of 2047
+    L.guess_roof_kernel(L.ROOF_READ_STREAMS, part, src, nbytes)
+    torch.cuda.synchronize()
+    seg = (nbytes // 16) // 16
+    assert float(part.sum()) == float(v[: 2 * 16 * seg].sum())
+    dst = torch.zeros(n, dtype=torch.float64, device="cuda")
+    L.guess_roof_kernel(L.ROOF_WRITE, dst, None, n * 8)
+    assert np.all(host(dst) == 1.0)
+    dst.zero_()
+    L.guess_roof_kernel(L.ROOF_COPY, dst, src, n * 8)
+    assert np.array_equal(host(dst), v)
