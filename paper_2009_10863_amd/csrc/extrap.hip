@@ -200,7 +200,7 @@ int launch_widen(int dtype, const void *src, double scale, double *out, int64_t 
 
 template <int DT, int K>
 static void run_form(const ExtrapArgs &a, double *x0, int64_t N, int grid, hipStream_t s, KEvents *ev) {
-    klaunch(ev, 0, extrap_form_kernel<DT, K>, grid, kBlock, s, a, x0, N);
+    klaunch_sh(ev, 0, extrap_form_kernel<DT, K>, grid, kBlock, gather_lds(), s, a, x0, N);
 }
 
 template <int DT>

@@ -92,6 +92,14 @@ int write_blocks() {
     return v;
 }
 
+int gather_lds() {
+    static const int v = [] {
+        int x = env_int("LIBGUESS_GATHER_LDS", 65536);
+        return x < 0 ? 0 : (x > 65536 ? 65536 : x);
+    }();
+    return v;
+}
+
 int reduce_blocks() {
     static const int v = [] {
         int x = env_int("LIBGUESS_REDUCE_BLOCKS", 1024);

@@ -19,13 +19,17 @@ struct KEvents {
 };
 
 template <typename... Args, typename F = void (*)(Args...)>
-inline void klaunch(KEvents *ev, int i, F f, int grid, int block, hipStream_t s, Args... args) {
+inline void klaunch_sh(KEvents *ev, int i, F f, int grid, int block, size_t shmem, hipStream_t s, Args... args) {
     if (ev) {
-        hipExtLaunchKernelGGL(f, dim3(grid), dim3(block), 0, s, ev->start[i], ev->stop[i], 0, args...);
+        hipExtLaunchKernelGGL(f, dim3(grid), dim3(block), shmem, s, ev->start[i], ev->stop[i], 0, args...);
         ev->count = i + 1;
     } else {
-        hipLaunchKernelGGL(f, dim3(grid), dim3(block), 0, s, args...);
+        hipLaunchKernelGGL(f, dim3(grid), dim3(block), shmem, s, args...);
     }
+}
+template <typename... Args, typename F = void (*)(Args...)>
+inline void klaunch(KEvents *ev, int i, F f, int grid, int block, hipStream_t s, Args... args) {
+    klaunch_sh<Args...>(ev, i, f, grid, block, 0, s, args...);
 }
 
 // Device-resident state of a projection history.  Decisions (restart,
@@ -168,6 +172,10 @@ int launch_gaussian_rhs(int n, const double *center, double sigma, double amp, d
 int grid_cap();
 // workgroups of the Gram-Schmidt write pass (LIBGUESS_WRITE_BLOCKS; 0: one chunk per thread)
 int write_blocks();
+// LDS bytes reserved (unused) by each workgroup of the kernels that combine many stored
+// vectors into one (extrapolation, projection combination), which caps how many of their
+// workgroups a CU holds at once (LIBGUESS_GATHER_LDS, default 65536: two per CU)
+int gather_lds();
 int reduce_blocks();
 bool march_enabled();
 

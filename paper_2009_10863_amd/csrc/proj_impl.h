@@ -881,7 +881,7 @@ void proj_form_dt(const ProjBufs &p, const double *b, double *x0, hipStream_t s,
     const int gr = stream_grid(nchunks(a.N), reduce_blocks());
     klaunch(ev, 0, proj_dots_kernel<DT, VF>, gr, kBlock, s, a, b);
     klaunch(ev, 1, proj_fin_kernel<FIN_DOTS, VF, DT>, 1, kBlock, s, a, gr);
-    klaunch(ev, 2, proj_combine_kernel<DT>, stream_grid(nchunks(a.N), grid_cap()), kBlock, s, a, x0);
+    klaunch_sh(ev, 2, proj_combine_kernel<DT>, stream_grid(nchunks(a.N), grid_cap()), kBlock, gather_lds(), s, a, x0);
 }
 
 template <int DT, int VF>

@@ -458,7 +458,7 @@ void raw_form_dt(const RawBufs &p, const double *b, double *x0, hipStream_t s, K
     const int gr = stream_grid(nchunks(a.N), reduce_blocks());
     klaunch(ev, 0, raw_dots_kernel<DT>, gr, kBlock, s, a, b);
     klaunch(ev, 1, raw_solve_kernel<DT>, 1, kBlock, s, a, gr);
-    klaunch(ev, 2, raw_combine_kernel<DT>, stream_grid(nchunks(a.N), grid_cap()), kBlock, s, a, x0);
+    klaunch_sh(ev, 2, raw_combine_kernel<DT>, stream_grid(nchunks(a.N), grid_cap()), kBlock, gather_lds(), s, a, x0);
 }
 
 template <int DT>
