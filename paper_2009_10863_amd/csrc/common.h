@@ -54,8 +54,10 @@ template <> __device__ __forceinline__ _Float16 to_store<GUESS_F16>(double v) {
     // The FP32 value is made opaque so that the compiler cannot merge the two
     // conversions into one direct FP64 -> FP16 rounding (which differs from
     // the two-step rounding when the FP32 value lands on an FP16 midpoint).
+    // Not volatile: the empty asm has no side effects, so it does not hold
+    // back the scheduling of the loads and stores around it.
     float f = (float)v;
-    asm volatile("" : "+v"(f));
+    asm("" : "+v"(f));
     return (_Float16)f;
 }
 template <> __device__ __forceinline__ uint16_t to_store<GUESS_BF16>(double v) {

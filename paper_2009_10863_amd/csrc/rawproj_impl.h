@@ -466,7 +466,9 @@ void raw_update_dt(const RawBufs &p, const Grid &g, const double *x, hipStream_t
     const RawArgs a = make_raw_args(p);
     const int gs = stream_grid(nchunks(a.N), grid_cap());
     int k = 0;
-    klaunch(ev, k++, raw_store_kernel<DT>, gs, kBlock, s, a, x);
+    // FP16: one atomic max per workgroup on one word, so the store runs on the reduction grid
+    klaunch(ev, k++, raw_store_kernel<DT>, DT == GUESS_F16 ? stream_grid(nchunks(a.N), reduce_blocks()) : gs, kBlock,
+            s, a, x);
     if constexpr (DT == GUESS_F16) klaunch(ev, k++, raw_fix_kernel<DT>, gs, kBlock, s, a, x);
     int ga = stream_grid(nchunks(a.N), reduce_blocks());
     if (march_ok(g) && march_enabled()) {
