@@ -92,6 +92,11 @@ int write_blocks() {
     return v;
 }
 
+bool raw_march() {
+    static const bool v = env_int("LIBGUESS_RAW_MARCH", 0) != 0;
+    return v;
+}
+
 int gather_lds() {
     static const int v = [] {
         int x = env_int("LIBGUESS_GATHER_LDS", 65536);

@@ -176,6 +176,9 @@ int write_blocks();
 // vectors into one (extrapolation, projection combination), which caps how many of their
 // workgroups a CU holds at once (LIBGUESS_GATHER_LDS, default 65536: two per CU)
 int gather_lds();
+// the raw-solution projection's operator apply in the z-marching form also for 2-byte formats
+// (LIBGUESS_RAW_MARCH, default 0; FP32 always marches)
+bool raw_march();
 int reduce_blocks();
 bool march_enabled();
 

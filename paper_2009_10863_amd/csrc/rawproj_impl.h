@@ -471,7 +471,9 @@ void raw_update_dt(const RawBufs &p, const Grid &g, const double *x, hipStream_t
             s, a, x);
     if constexpr (DT == GUESS_F16) klaunch(ev, k++, raw_fix_kernel<DT>, gs, kBlock, s, a, x);
     int ga = stream_grid(nchunks(a.N), reduce_blocks());
-    if (march_ok(g) && march_enabled()) {
+    // 2-byte formats: the chunk form (256^3, FP16 / BF16: 47 against 64 us in the z-march, whose
+    // plane-by-plane latency a 2-byte operand does not hide); FP32: the z-march (within 5 %)
+    if (march_ok(g) && march_enabled() && (DT == GUESS_F32 || raw_march())) {
         const int wgs = g.kx ? resident_wgs<raw_apply_march_kernel<DT, true>>()
                              : resident_wgs<raw_apply_march_kernel<DT, false>>();
         const March m = make_march(g, wgs);
