@@ -75,3 +75,55 @@ def test_read_write_split_and_mixed_roof():
     assert bench.mixed_roof(1.0, 0.0, 6000.0, 5000.0) == 6000.0
     assert bench.mixed_roof(0.0, 1.0, 6000.0, 5000.0) == 5000.0
     assert abs(bench.mixed_roof(1.0, 1.0, 6000.0, 4000.0) - 4800.0) < 1e-9
+
+
+def test_traffic_summary_from_counter_csvs(tmp_path, monkeypatch):
+    """--traffic-summary: counters scaled by the copy kernel's reading, totals over the launches
+    that moved data (a launch that returns at once is left out), beside the profiled run's own
+    algorithmic bytes; the summary names its sources' hash so that the bench can tell it is
+    current."""
+    import csv
+    import json
+    import types
+
+    def write(folder, rows):
+        folder.mkdir()
+        with open(folder / "x_counter_collection.csv", "w", newline="") as f:
+            w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+            w.writeheader()
+            for r in rows:
+                w.writerow(r)
+
+    kib = 1024.0
+    row = lambda k, c, v: {"Kernel_Name": k, "Counter_Name": c, "Counter_Value": v}  # noqa: E731
+    # copy kernel of 1 GiB -> 1 GiB: FETCH_SIZE reads half, WRITE_SIZE all
+    write(tmp_path / "fc", [row("lg::copy_kernel(a)", "FETCH_SIZE", (1 << 30) / 2 / kib)])
+    write(tmp_path / "wc", [row("lg::copy_kernel(a)", "WRITE_SIZE", (1 << 30) / kib)])
+    # proj_dots: two launches of 800 KiB read (counter reads half), one that returned at once
+    write(tmp_path / "f", [row("void lg::proj_dots_kernel<0, 0>(a)", "FETCH_SIZE", 400.0)] * 2 +
+          [row("void lg::proj_dots_kernel<0, 0>(a)", "FETCH_SIZE", 0.5),
+           row("void lg::pcg_b_kernel<false>(a)", "FETCH_SIZE", 8.0)])
+    write(tmp_path / "w", [row("void lg::proj_dots_kernel<0, 0>(a)", "WRITE_SIZE", 1.0)] * 2 +
+          [row("void lg::pcg_b_kernel<false>(a)", "WRITE_SIZE", 8.0)])
+    run = {"config": {"n": 16, "workload": "test"}, "kernels": {"proj_dots": {"bytes_per_launch": 800 * kib,
+                                                                               "launches": 2}}}
+    (tmp_path / "f" / "bench.json").write_text(json.dumps(run) + "\n")
+    profiles = tmp_path / "root" / "profiles"
+    profiles.mkdir(parents=True)
+    for f in bench.TRAFFIC_SOURCES:
+        (tmp_path / "root" / f).parent.mkdir(parents=True, exist_ok=True)
+        (tmp_path / "root" / f).write_text(f)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path / "root"))
+    args = types.SimpleNamespace(traffic_summary=[str(tmp_path / d) for d in ("f", "w", "fc", "wc")])
+    bench.traffic_summary(args)
+    rec = {}
+    for line in open(profiles / "hbm_traffic.txt"):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            rec[k.strip()] = v.strip()
+    assert float(rec["fetch_scale"]) == 2.0 and float(rec["write_scale"]) == 1.0
+    assert float(rec["proj_dots.read_bytes_per_launch"]) == 800 * kib
+    assert float(rec["proj_dots.write_bytes_per_launch"]) == kib
+    assert rec["proj_dots.ratio"] == f"{801 / 800:.4f}"
+    assert float(rec["pcg_b.algorithmic_bytes_per_launch"]) == 24 * 16 ** 3
+    assert bench.hbm_traffic("proj_dots") == (801 * kib, 800 * kib)
