@@ -319,7 +319,6 @@ def traffic_summary(args):
         rows.append(f"{k}.ratio = {(rd + wr) / alg:.4f}")
         rows.append(f"{k}.dispatches = {nf} fetch, {nw} write" +
                     (f" (bench launches {launches})" if launches is not None else ""))
-    cmd = run.get("command", "")
     head = [
         f"# HBM bytes per launch, {run['config']['workload']}: FETCH_SIZE and WRITE_SIZE (KiB per dispatch,",
         "# one rocprofv3 --pmc run each), scaled by what the same counters read for the plain copy kernel",
@@ -342,7 +341,6 @@ def traffic_summary(args):
         f"fetch_scale = {fscale:.6f}",
         f"write_scale = {wscale:.6f}",
     ]
-    del cmd
     out = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     with open(out, "w") as f:
         f.write("\n".join(head + rows) + "\n")
