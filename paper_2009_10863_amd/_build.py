@@ -25,11 +25,16 @@ LIB = os.path.join(PKG, "_lib", "libguess.so")
 # extrapolation kernels gained nothing, so they keep the default).  The
 # projection kernels are compiled once per storage format and variant (bit 1:
 # rolling QR, bit 2: l2 inner product), the raw-solution projection once per
-# storage format.
+# storage format.  The FP16 / BF16 projection units are built for at least three
+# waves per SIMD: their 2-byte columns keep fewer bytes in flight per wave (at
+# 256^3, M = 8: fused apply 90 -> 81 us, write pass 104 -> 94 us, rolling write
+# pass 132-140 -> 95 us; FP32 ran 1 % slower that way, so FP32 and FP64 keep the
+# default).
 _DTYPES = ["GUESS_F64", "GUESS_F32", "GUESS_F16", "GUESS_BF16"]
 _MAX_ILP = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
 UNITS = [("proj_inst.hip", f"proj_{dt[6:].lower()}_v{vf}",
-          [f"-DLG_PROJ_DT={dt}", f"-DLG_PROJ_VF={vf}", *_MAX_ILP])
+          [f"-DLG_PROJ_DT={dt}", f"-DLG_PROJ_VF={vf}", *_MAX_ILP,
+           *(["-DLG_WAVES_MIN=3"] if dt in ("GUESS_F16", "GUESS_BF16") else [])])
          for dt in _DTYPES for vf in range(4)]
 UNITS += [("rawproj_inst.hip", f"rawproj_{dt[6:].lower()}", [f"-DLG_RAW_DT={dt}", *_MAX_ILP]) for dt in _DTYPES]
 UNITS += [("pcg.hip", "pcg", [*_MAX_ILP, "-DLG_WAVES_MIN=2"])]
