@@ -162,7 +162,7 @@ def parse():
     p.add_argument("--maxit", type=int, default=5000)
     p.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     p.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
-    p.add_argument("--cpu-steps", type=int, default=6)
+    p.add_argument("--cpu-steps", type=int, default=10)
     p.add_argument("--no-small-sequence", dest="small", action="store_false", default=True,
                    help="skip the 32^3 whole-sequence run (e.g. under a profiler)")
     p.add_argument("--precision-steps", type=int, default=10,
