@@ -326,16 +326,16 @@ def traffic_summary(args):
         "# of the guess kernels from the profiled run's own JSON line, of PCG's kernels per unknown",
         "# (pcg_a_xupdate: the odd iterations that also update x, 56 B; pcg_a: 32 B; pcg_b: 24 B).",
         "# Dispatches that return at once (reading < 1 % of the kernel's median) are left out.",
-        "# Valid while the sources below hash to sha256.  Commands (from /tmp, TMPDIR=/tmp):",
+        "# Valid while the sources below hash to sha256.  Commands (from /tmp, TMPDIR=/tmp; the four",
+        "# output folders as given to --traffic-summary):",
         "#   rocprofv3 --pmc FETCH_SIZE -f csv --kernel-include-regex \"extrap_form|ring_store|proj_|copy_kernel|pcg_\" "
-        "-d gpurun_out/prof_FETCH_SIZE -o bench -- python3 bench.py --steps 15 --warmup 0 --no-cpu-baseline "
-        "--no-small-sequence --precision-steps 0 > gpurun_out/prof_FETCH_SIZE/bench.json",
-        "#   (the same with WRITE_SIZE and gpurun_out/prof_WRITE_SIZE)",
-        "#   rocprofv3 --pmc FETCH_SIZE -f csv --kernel-include-regex copy_kernel -d gpurun_out/prof_FETCH_SIZE_copy "
+        f"-d {fdir} -o bench -- python3 bench.py --steps 15 --warmup 0 --no-cpu-baseline "
+        f"--no-small-sequence --precision-steps 0 > {fdir}/bench.json",
+        f"#   (the same with WRITE_SIZE and {wdir})",
+        f"#   rocprofv3 --pmc FETCH_SIZE -f csv --kernel-include-regex copy_kernel -d {fcopy} "
         "-o copy -- python3 bench.py --calibrate-copy",
-        "#   (the same with WRITE_SIZE and gpurun_out/prof_WRITE_SIZE_copy)",
-        "#   python3 bench.py --traffic-summary gpurun_out/prof_FETCH_SIZE gpurun_out/prof_WRITE_SIZE "
-        "gpurun_out/prof_FETCH_SIZE_copy gpurun_out/prof_WRITE_SIZE_copy",
+        f"#   (the same with WRITE_SIZE and {wcopy})",
+        f"#   python3 bench.py --traffic-summary {fdir} {wdir} {fcopy} {wcopy}",
         f"sources = {','.join(sorted(TRAFFIC_SOURCES))}",
         f"sha256 = {h.hexdigest()}",
         f"fetch_scale = {fscale:.6f}",
