@@ -130,7 +130,7 @@ def parse():
                    help="projection: relative rejection threshold of a new vector (<= 0: the library's "
                         "default for the storage format, 1e-6 for FP64)")
     p.add_argument("--precision-dtypes", default="f32,f16,bf16")
-    p.add_argument("--precision-methods", default="extrap,proj,proj_raw",
+    p.add_argument("--precision-methods", default="extrap,proj,proj_raw,projqr_raw",
                    help="methods of the reduced-precision runs (proj_raw: reduced precision only)")
     p.add_argument("--progress", action="store_true", help="print a line to stderr after every step")
     p.add_argument("--fields", choices=("one", "ins"), default="one",
