@@ -143,7 +143,11 @@ __global__ __launch_bounds__(kBlock) void ring_store_f16_kernel(const double *__
         double m = wmax[0];
 #pragma unroll
         for (int w = 1; w < kWaves; ++w) m = nanmax(m, wmax[w]);
-        atomicMax(&rs->maxbits[gen], (unsigned long long)__double_as_longlong(m));
+        // the running maximum only grows: a workgroup whose maximum does not exceed a value it
+        // reads there has nothing to add (a stale read costs one atomic, never a wrong result)
+        const unsigned long long mb = (unsigned long long)__double_as_longlong(m);
+        if (mb > __hip_atomic_load(&rs->maxbits[gen], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&rs->maxbits[gen], mb);
         if (blockIdx.x == 0) {
             rs->e_used[gen] = e;
             rs->maxbits[gen ^ 1] = 0ull;   // the next store's accumulator

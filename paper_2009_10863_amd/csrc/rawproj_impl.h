@@ -118,7 +118,10 @@ __global__ __launch_bounds__(kBlock) void raw_store_kernel(RawArgs a, const doub
             double t = wmax[0];
 #pragma unroll
             for (int w = 1; w < kWaves; ++w) t = nanmax(t, wmax[w]);
-            atomicMax(&st->maxbits, (unsigned long long)__double_as_longlong(t));
+            // the running maximum only grows (see the ring store): skip what cannot raise it
+            const unsigned long long tb = (unsigned long long)__double_as_longlong(t);
+            if (tb > __hip_atomic_load(&st->maxbits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                atomicMax(&st->maxbits, tb);
             if (blockIdx.x == 0) st->e_used = e;
         }
     }
