@@ -968,6 +968,8 @@ def main():
             "guess_ms_per_step": S["guess_ms"] / args.steps,
             "pcg_iters_per_step": float(np.mean(S["iters"])),
             "pcg_ms_per_step": S["solve_ms"] / args.steps,
+            # wall time of the solves (initial residual, iterations, host loop) per iteration
+            "pcg_us_per_iteration": S["solve_ms"] * 1e3 / max(1.0, float(np.sum(S["iters"]))),
             "max_relres": float(np.max(S["relres"])),
             "history_after_run": S["history"],
         }
