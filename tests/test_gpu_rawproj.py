@@ -122,6 +122,27 @@ def test_plane_wave_history(lib, method, dtype):
     assert check_rows(rows, label=f"{method} {dtype} plane waves") == T
 
 
+@pytest.mark.parametrize("method,dtype", [("projqr_raw", "f32")])
+def test_full_size_replay(lib, method, dtype):
+    """The benchmark's size, 256^3, M = 8, for the FP32 rolling window: ten random solutions (it
+    drops its oldest twice), every stored solution bit for bit, guesses to 1e-12 and the factor
+    against the oracle, with the z-marching apply at the size the benchmark runs it."""
+    announce(f"{method} {dtype} random 256^3")
+    n, M, T = 256, 8, 10
+    N = n ** 3
+    X = [v * (1.0 + 0.5 * q) for q, v in enumerate(synth.random_vectors(65, T, N))]
+    B = synth.random_vectors(66, T, N)
+    rows, ref, stored = run(lib, n, M, B, X, method, dtype)
+    check_stored(ref, stored, dtype, f"{method} {dtype} 256^3")
+    assert check_rows(rows, strict=True, label=f"{method} {dtype} 256^3") == T
+    check_factors(rows, f"{method} {dtype} 256^3")
+    ds = [r["d"] for r in rows]
+    if method == "projqr_raw":
+        assert ds == [min(q + 1, M) for q in range(T)] and rows[-1]["info"]["drops"] == T - M
+    else:
+        assert ds == [(q % M) + 1 for q in range(T)]
+
+
 def test_factor_is_the_cholesky_factor_of_the_gram_matrix(lib):
     announce("proj_raw factor")
     n, M, T = 8, 6, 9
