@@ -122,11 +122,12 @@ def test_plane_wave_history(lib, method, dtype):
     assert check_rows(rows, label=f"{method} {dtype} plane waves") == T
 
 
-@pytest.mark.parametrize("method,dtype", [("projqr_raw", "f32")])
+@pytest.mark.parametrize("method,dtype", [("projqr_raw", "f32"), ("proj_raw", "f16")])
 def test_full_size_replay(lib, method, dtype):
-    """The benchmark's size, 256^3, M = 8, for the FP32 rolling window: ten random solutions (it
-    drops its oldest twice), every stored solution bit for bit, guesses to 1e-12 and the factor
-    against the oracle, with the z-marching apply at the size the benchmark runs it."""
+    """The benchmark's size, 256^3, M = 8: ten random solutions (the rolling window drops its
+    oldest twice, the classic one restarts once), every stored solution bit for bit, guesses to
+    1e-12 and the factor against the oracle -- the z-marching apply (FP32) and the chunk-form
+    apply (FP16) at the size the benchmark runs them."""
     announce(f"{method} {dtype} random 256^3")
     n, M, T = 256, 8, 10
     N = n ** 3
